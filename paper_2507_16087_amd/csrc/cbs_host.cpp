@@ -1,0 +1,980 @@
+// Host runtime of the iterative Born solver: medium planner (Algorithm 1
+// preprocessing), workspace layout, iteration drivers (plain FP64 and FP32
+// with FP64 iterative refinement), and the C ABI of include/cbs.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cbs.h"
+#include "cbs_internal.h"
+
+using cd = std::complex<double>;
+
+namespace cbs {
+// kernels (cbs_kernels.hip)
+template <typename T>
+hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
+                       int pcols, bool wide, hipStream_t st);
+template <typename T>
+hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st);
+hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st);
+template <typename T>
+hipError_t launch_zero(cx<T>* p, int64_t n, hipStream_t st);
+hipError_t launch_rhs(const Geom& g, const cx<double>* sp, const cx<double>* su, const double* rhobar,
+                      const cx<double>* q, int physical, double il1s, double il2s, cx<double>* y64,
+                      cx<float>* y32, hipStream_t st);
+hipError_t launch_scale_in(const Geom& g, const cx<double>* p, const cx<double>* u, double sl1, double sl2,
+                           cx<double>* x, hipStream_t st);
+template <typename T>
+hipError_t launch_unscale(const Geom& g, const cx<T>* x, double il1s, double il2s, cx<double>* p,
+                          cx<double>* u, hipStream_t st);
+hipError_t launch_residual_out(const Geom& g, const cx<double>* r, double sl1, double sl2, cx<double>* rp,
+                               cx<double>* ru, hipStream_t st);
+hipError_t launch_convert(const cx<double>* r, cx<float>* y32, int64_t n, const Ctl* c, hipStream_t st);
+hipError_t launch_accumulate(cx<double>* x, const cx<float>* d, int64_t n, const Ctl* c, hipStream_t st);
+hipError_t launch_gradient(const Geom& g, const double* c, const double* rho, const double* alpha,
+                           const cx<double>* q, const double* const* gcen, const double* const* gst, double gmax,
+                           double omega, const cx<double>* sp, const cx<double>* su, const cx<double>* p,
+                           const cx<double>* u, const cx<double>* lp, const cx<double>* lu, double* gc,
+                           double* grho, double* galpha, hipStream_t st);
+int plan_tpc(int n, bool wide);
+bool plan_has_wide(int n);
+enum { MODE_CBS = 0, MODE_APPLY = 1 };
+}  // namespace cbs
+
+using namespace cbs;
+
+#define HIPOK(expr)                                   \
+    do {                                              \
+        if ((expr) != hipSuccess) return CBS_E_DEVICE; \
+    } while (0)
+
+namespace {
+
+const int kSizes[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+
+bool size_supported(int64_t n) {
+    for (int s : kSizes)
+        if (s == n) return true;
+    return false;
+}
+
+// ----------------------------------------------------------- pass config --
+// The passes of one iteration, and the column-tile width of each.
+struct Pass {
+    int kind;    // 0 contiguous forward (+prologue), 1 contiguous inverse (+epilogue),
+                 // 2 strided forward, 3 strided inverse, 4 axis-0 propagator
+    int axis;
+    int n;
+    int pcols;
+    bool wide;
+};
+
+struct PassSet {
+    Pass p[5];
+    int count;
+    int nparts;   // partial-sum slots written by the last pass
+};
+
+int pow2_floor_div(int64_t total, int cap) {
+    int p = 1;
+    while (p * 2 <= cap && total % (p * 2) == 0) p *= 2;
+    return p;
+}
+
+PassSet make_passes(const Geom& g, bool fp64) {
+    PassSet ps{};
+    const int last = g.ndim - 1;
+    const int pstr = fp64 ? 8 : 16;   // columns per strided tile: 128-byte row segments
+    auto strided = [&](int kind, int axis, bool wide) {
+        Pass p{};
+        p.kind = kind;
+        p.axis = axis;
+        p.n = g.n[axis];
+        p.wide = wide && plan_has_wide(p.n);
+        const int tpc = plan_tpc(p.n, p.wide);
+        p.pcols = pow2_floor_div(g.n[last], std::min(pstr, 256 / tpc));
+        return p;
+    };
+    auto contig = [&](int kind) {
+        Pass p{};
+        p.kind = kind;
+        p.axis = last;
+        p.n = g.n[last];
+        p.wide = false;
+        const int tpc = plan_tpc(p.n, false);
+        const int64_t pencils = g.ncell / g.n[last];
+        p.pcols = pow2_floor_div(pencils, std::min(fp64 ? 16 : 32, 256 / tpc));
+        return p;
+    };
+    int k = 0;
+    ps.p[k++] = contig(0);
+    if (g.ndim == 3) ps.p[k++] = strided(2, 1, false);
+    ps.p[k++] = strided(4, 0, fp64);
+    if (g.ndim == 3) ps.p[k++] = strided(3, 1, false);
+    ps.p[k++] = contig(1);
+    ps.count = k;
+    const Pass& lp = ps.p[k - 1];
+    ps.nparts = (int)((g.ndim + 1) * (g.ncell / ((int64_t)lp.n * lp.pcols)));
+    return ps;
+}
+
+// ------------------------------------------------------------- planner --
+// Periodic distance of position t from the interior [L, n-1-L], over L+1/2.
+double layer_frac(double t, int n, int L) {
+    if (L <= 0) return 0.0;
+    const double lo = L, hi = n - 1 - L;
+    if (t >= lo && t <= hi) return 0.0;
+    const double d = (t > hi) ? std::min(t - hi, lo + n - t) : std::min(lo - t, t + n - hi);
+    return d / (L + 0.5);
+}
+
+struct Circle {
+    double x, y, r;
+};
+
+bool in_circle(const Circle& c, double px, double py) {
+    return std::hypot(px - c.x, py - c.y) <= c.r * (1.0 + 1e-12) + 1e-300;
+}
+
+Circle from2(double ax, double ay, double bx, double by) {
+    return {(ax + bx) * 0.5, (ay + by) * 0.5, 0.5 * std::hypot(ax - bx, ay - by)};
+}
+
+Circle from3(double ax, double ay, double bx, double by, double cx_, double cy_) {
+    const double ux = bx - ax, uy = by - ay, vx = cx_ - ax, vy = cy_ - ay;
+    const double d = 2.0 * (ux * vy - uy * vx);
+    if (std::fabs(d) < 1e-300) {
+        Circle c1 = from2(ax, ay, bx, by), c2 = from2(ax, ay, cx_, cy_), c3 = from2(bx, by, cx_, cy_);
+        Circle best = c1;
+        if (c2.r > best.r) best = c2;
+        if (c3.r > best.r) best = c3;
+        return best;
+    }
+    const double u2 = ux * ux + uy * uy, v2 = vx * vx + vy * vy;
+    const double ox = (vy * u2 - uy * v2) / d, oy = (ux * v2 - vx * u2) / d;
+    return {ax + ox, ay + oy, std::hypot(ox, oy)};
+}
+
+// Smallest circle enclosing the points (Welzl's incremental algorithm).  An
+// exact pre-filter first drops points strictly inside the octagon spanned by
+// the extreme points in eight directions: such points are interior to the
+// convex hull and cannot lie on the minimum enclosing circle.
+Circle min_circle(const std::vector<cd>& pts) {
+    const size_t n = pts.size();
+    if (n == 0) return {0, 0, 0};
+    const double dirs[8][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
+    size_t ext[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double best[8];
+    for (int d = 0; d < 8; ++d) best[d] = -INFINITY;
+    for (size_t i = 0; i < n; ++i)
+        for (int d = 0; d < 8; ++d) {
+            const double v = pts[i].real() * dirs[d][0] + pts[i].imag() * dirs[d][1];
+            if (v > best[d]) {
+                best[d] = v;
+                ext[d] = i;
+            }
+        }
+    std::vector<cd> poly;
+    for (int d = 0; d < 8; ++d) {
+        const cd p = pts[ext[d]];
+        if (poly.empty() || std::abs(poly.back() - p) > 0) poly.push_back(p);
+    }
+    while (poly.size() > 1 && std::abs(poly.front() - poly.back()) == 0) poly.pop_back();
+    std::vector<cd> keep;
+    keep.reserve(1024);
+    const size_t m = poly.size();
+    for (size_t i = 0; i < n; ++i) {
+        bool inside = m >= 3;
+        for (size_t e = 0; e < m && inside; ++e) {
+            const cd a = poly[e], b = poly[(e + 1) % m];
+            const double cr = (b.real() - a.real()) * (pts[i].imag() - a.imag()) -
+                              (b.imag() - a.imag()) * (pts[i].real() - a.real());
+            // counter-clockwise octagon: interior points are strictly left of every edge
+            const double scale = std::abs(b - a) * (std::abs(pts[i] - a) + 1e-300);
+            if (!(cr > 1e-9 * scale)) inside = false;
+        }
+        if (!inside) keep.push_back(pts[i]);
+    }
+    // deterministic shuffle
+    uint64_t s = 0x2545F4914F6CDD1Dull;
+    for (size_t i = keep.size(); i > 1; --i) {
+        s ^= s << 13;
+        s ^= s >> 7;
+        s ^= s << 17;
+        std::swap(keep[i - 1], keep[s % i]);
+    }
+    Circle c{keep[0].real(), keep[0].imag(), 0.0};
+    for (size_t i = 1; i < keep.size(); ++i) {
+        if (in_circle(c, keep[i].real(), keep[i].imag())) continue;
+        c = {keep[i].real(), keep[i].imag(), 0.0};
+        for (size_t j = 0; j < i; ++j) {
+            if (in_circle(c, keep[j].real(), keep[j].imag())) continue;
+            c = from2(keep[i].real(), keep[i].imag(), keep[j].real(), keep[j].imag());
+            for (size_t k = 0; k < j; ++k)
+                if (!in_circle(c, keep[k].real(), keep[k].imag()))
+                    c = from3(keep[i].real(), keep[i].imag(), keep[j].real(), keep[j].imag(), keep[k].real(),
+                              keep[k].imag());
+        }
+    }
+    return c;
+}
+
+double median(std::vector<double>& v) {
+    const size_t n = v.size(), h = n / 2;
+    std::nth_element(v.begin(), v.begin() + h, v.end());
+    const double hi = v[h];
+    if (n % 2) return hi;
+    const double lo = *std::max_element(v.begin(), v.begin() + h);
+    return 0.5 * (lo + hi);
+}
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- medium --
+struct cbs_medium_s {
+    Geom g;
+    cbs_grid grid;
+    double gmax, beta, nu;
+    cd a1, a2;
+    double lam1, lam2;
+    PassSet ps64, ps32;
+    void* dev = nullptr;
+    // device pointers into dev
+    double *rhobar64, *c64, *rho64, *alpha64;
+    cx<double>* q64;
+    float* rhobar32;
+    cx<float>* q32;
+    double *gc64[3], *gs64[3], *kv64[3];
+    cx<double> *sh64[3], *tw64[3];
+    float *gc32[3], *gs32[3], *kv32[3];
+    cx<float> *sh32[3], *tw32[3];
+};
+
+namespace {
+
+template <typename T>
+struct Tables;
+template <>
+struct Tables<double> {
+    static void fill(const cbs_medium_s* m, Slot<double>& s) {
+        s.rhobar = m->rhobar64;
+        s.q = m->q64;
+        for (int d = 0; d < 3; ++d) {
+            s.gc[d] = m->gc64[d];
+            s.gs[d] = m->gs64[d];
+            s.kv[d] = m->kv64[d];
+            s.sh[d] = m->sh64[d];
+            s.tw[d] = m->tw64[d];
+        }
+    }
+};
+template <>
+struct Tables<float> {
+    static void fill(const cbs_medium_s* m, Slot<float>& s) {
+        s.rhobar = m->rhobar32;
+        s.q = m->q32;
+        for (int d = 0; d < 3; ++d) {
+            s.gc[d] = m->gc32[d];
+            s.gs[d] = m->gs32[d];
+            s.kv[d] = m->kv32[d];
+            s.sh[d] = m->sh32[d];
+            s.tw[d] = m->tw32[d];
+        }
+    }
+};
+
+template <typename T>
+cx<T> tocx(cd v) {
+    return {(T)v.real(), (T)v.imag()};
+}
+
+template <typename T>
+Slot<T> make_slot(const cbs_medium_s* m, cx<T>* x, cx<T>* w, const cx<T>* y, Ctl* ctl, double* partials,
+                  int adjoint) {
+    Slot<T> s{};
+    s.x = x;
+    s.w = w;
+    s.y = y;
+    Tables<T>::fill(m, s);
+    s.omega = (T)m->grid.omega;
+    s.gmax = (T)m->gmax;
+    s.nu = (T)m->nu;
+    s.a1re = (T)m->a1.real();
+    s.a1im = (T)m->a1.imag();
+    s.a2re = (T)m->a2.real();
+    s.a2im = (T)m->a2.imag();
+    s.inv_lam1 = (T)(1.0 / m->lam1);
+    s.inv_lam2 = (T)(1.0 / m->lam2);
+    s.s = (T)std::sqrt(m->lam1 * m->lam2);
+    s.inv_ntot = (T)(1.0 / (double)m->g.ncell);
+    const cd al1 = m->a1 + m->lam1, al2 = m->a2 + m->lam2;
+    s.al1 = tocx<T>(al1);
+    s.al2 = tocx<T>(al2);
+    s.ca = tocx<T>(m->lam1 / al1);
+    s.cp = tocx<T>(m->lam2 * al1);
+    s.al12 = tocx<T>(al1 * al2);
+    s.adjoint = adjoint;
+    s.ctl = ctl;
+    s.partials = partials;
+    return s;
+}
+
+// One CBS iteration (MODE_CBS) or one residual evaluation (MODE_APPLY) for
+// nslots same-shape slots.
+template <typename T>
+hipError_t run_passes(const cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T>* dslots, int nslots,
+                      hipStream_t st) {
+    for (int i = 0; i < ps.count; ++i) {
+        const Pass& p = ps.p[i];
+        hipError_t e = launch_pass<T>(p.kind, mode, dslots, nslots, m->g, p.axis, p.n, p.pcols, p.wide, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_reduce<T>(mode == MODE_CBS, dslots, ps.nparts, nslots, st);
+}
+
+struct Layout {
+    size_t off_slot64, off_ctl64, off_part64, off_x64, off_w64, off_y64;
+    size_t off_slot32, off_ctl32, off_part32, off_d32, off_w32, off_y32;
+    size_t total;
+};
+
+Layout layout_for(const cbs_medium_s* m, int prec) {
+    Layout L{};
+    const size_t nf = (size_t)(m->g.ndim + 1) * m->g.ncell;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.off_slot64 = take(sizeof(Slot<double>));
+    L.off_ctl64 = take(sizeof(Ctl));
+    L.off_part64 = take(sizeof(double) * 2 * (size_t)std::max(m->ps64.nparts, 1));
+    L.off_x64 = take(nf * sizeof(cx<double>));
+    L.off_w64 = take(nf * sizeof(cx<double>));
+    L.off_y64 = take(nf * sizeof(cx<double>));
+    if (prec == CBS_FP32_REFINED) {
+        L.off_slot32 = take(sizeof(Slot<float>));
+        L.off_ctl32 = take(sizeof(Ctl));
+        L.off_part32 = take(sizeof(double) * 2 * (size_t)std::max(m->ps32.nparts, 1));
+        L.off_d32 = take(nf * sizeof(cx<float>));
+        L.off_w32 = take(nf * sizeof(cx<float>));
+        L.off_y32 = take(nf * sizeof(cx<float>));
+    }
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+cbs_status validate_grid(const cbs_grid* g) {
+    if (!g) return CBS_E_INVALID;
+    if (g->ndim != 2 && g->ndim != 3) return CBS_E_UNSUPPORTED;
+    if (!(g->dx > 0) || !(g->omega > 0) || !std::isfinite(g->dx) || !std::isfinite(g->omega))
+        return CBS_E_INVALID;
+    for (int d = 0; d < g->ndim; ++d) {
+        if (!size_supported(g->n[d])) return CBS_E_UNSUPPORTED;
+        if (g->pml_cells < 0 || 2 * (int64_t)g->pml_cells >= g->n[d]) return CBS_E_INVALID;
+    }
+    const double beta = g->beta == 0 ? 0.95 : g->beta;
+    const double nu = g->nu == 0 ? 0.9 : g->nu;
+    if (!(beta > 0) || !std::isfinite(beta)) return CBS_E_INVALID;
+    if (!(nu > 0) || !std::isfinite(nu)) return CBS_E_INVALID;
+    if (g->shift_rule != 0 && g->shift_rule != 1) return CBS_E_INVALID;
+    return CBS_OK;
+}
+
+struct StreamGuard {
+    hipStream_t s;
+};
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double* rho, const double* alpha,
+                             int32_t ptr_kind, void* hip_stream, cbs_medium* out) {
+    if (!out) return CBS_E_INVALID;
+    *out = nullptr;
+    cbs_status vs = validate_grid(grid);
+    if (vs != CBS_OK) return vs;
+    if (!c || !rho || !alpha) return CBS_E_INVALID;
+    if (ptr_kind != CBS_PTR_HOST && ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int D = grid->ndim;
+    Geom g{};
+    g.ndim = D;
+    g.ncell = 1;
+    for (int d = 0; d < 3; ++d) g.n[d] = d < D ? (int)grid->n[d] : 1;
+    for (int d = 0; d < D; ++d) g.ncell *= g.n[d];
+    const int64_t N = g.ncell;
+
+    // host copies of the medium
+    std::vector<double> hc(N), hr(N), ha(N);
+    if (ptr_kind == CBS_PTR_DEVICE) {
+        HIPOK(hipMemcpyAsync(hc.data(), c, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipMemcpyAsync(hr.data(), rho, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipMemcpyAsync(ha.data(), alpha, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(hc.data(), c, N * sizeof(double));
+        std::memcpy(hr.data(), rho, N * sizeof(double));
+        std::memcpy(ha.data(), alpha, N * sizeof(double));
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (!(hc[i] > 0) || !(hr[i] > 0) || !(ha[i] >= 0) || !std::isfinite(hc[i]) || !std::isfinite(hr[i]) ||
+            !std::isfinite(ha[i]))
+            return CBS_E_INVALID;
+
+    cbs_medium_s* m = new (std::nothrow) cbs_medium_s();
+    if (!m) return CBS_E_NOMEM;
+    m->g = g;
+    m->grid = *grid;
+    m->gmax = grid->pml_gamma_max > 0 ? grid->pml_gamma_max : grid->omega;
+    m->beta = grid->beta == 0 ? 0.95 : grid->beta;
+    m->nu = grid->nu == 0 ? 0.9 : grid->nu;
+    const double w = grid->omega, dx = grid->dx;
+    const int L = grid->pml_cells;
+
+    // per-axis layer profiles r^2 at centres and staggered points
+    std::vector<double> prof_c[3], prof_s[3];
+    for (int d = 0; d < 3; ++d) {
+        prof_c[d].assign(g.n[d], 0.0);
+        prof_s[d].assign(g.n[d], 0.0);
+        if (d >= D) continue;
+        for (int i = 0; i < g.n[d]; ++i) {
+            const double rc = layer_frac(i, g.n[d], L), rs = layer_frac(i + 0.5, g.n[d], L);
+            prof_c[d][i] = rc * rc;
+            prof_s[d][i] = rs * rs;
+        }
+    }
+    // q, staggered density, diagonal values for the shifts
+    std::vector<cd> q(N);
+    std::vector<double> rb((size_t)D * N);
+    std::vector<cd> Du((size_t)D * N), Dp(N);
+    int64_t stride[3] = {1, 1, 1};
+    for (int d = D - 2; d >= 0; --d) stride[d] = stride[d + 1] * g.n[d + 1];
+    for (int64_t i = 0; i < N; ++i) {
+        int ix[3] = {0, 0, 0};
+        int64_t r = i;
+        for (int d = D - 1; d >= 0; --d) {
+            ix[d] = (int)(r % g.n[d]);
+            r /= g.n[d];
+        }
+        const double cc = hc[i];
+        q[i] = cd(1.0, -2.0 * ha[i] * cc / w) / (hr[i] * cc * cc);
+        double gsum = 0.0;
+        for (int d = 0; d < D; ++d) gsum += prof_c[d][ix[d]];
+        const double gam = m->gmax * gsum;
+        Dp[i] = cd(gam, w) * q[i];
+        for (int e = 0; e < D; ++e) {
+            const int64_t nb = (ix[e] + 1 < g.n[e]) ? i + stride[e] : i - (int64_t)(g.n[e] - 1) * stride[e];
+            const double rbar = 0.5 * (hr[i] + hr[nb]);
+            rb[(size_t)e * N + i] = rbar;
+            double gs = 0.0;
+            for (int d = 0; d < D; ++d) gs += (d == e) ? prof_s[d][ix[d]] : prof_c[d][ix[d]];
+            Du[(size_t)e * N + i] = cd(rbar * (m->gmax * gs), rbar * w);
+        }
+    }
+    // shifts (Algorithm 1 preprocessing) and scales (eq. C)
+    if (grid->shift_rule == 1) {
+        std::vector<double> v(Du.size());
+        for (size_t i = 0; i < Du.size(); ++i) v[i] = Du[i].real();
+        const double r1 = median(v);
+        for (size_t i = 0; i < Du.size(); ++i) v[i] = Du[i].imag();
+        m->a1 = cd(r1, median(v));
+        v.resize(Dp.size());
+        for (size_t i = 0; i < Dp.size(); ++i) v[i] = Dp[i].real();
+        const double r2 = median(v);
+        for (size_t i = 0; i < Dp.size(); ++i) v[i] = Dp[i].imag();
+        m->a2 = cd(r2, median(v));
+    } else {
+        Circle c1 = min_circle(Du), c2 = min_circle(Dp);
+        m->a1 = cd(c1.x, c1.y);
+        m->a2 = cd(c2.x, c2.y);
+    }
+    double r1 = 0.0, r2 = 0.0;
+    for (const cd& v : Du) r1 = std::max(r1, std::abs(v - m->a1));
+    for (const cd& v : Dp) r2 = std::max(r2, std::abs(v - m->a2));
+    m->lam1 = std::max(r1, 1e-3 * std::abs(m->a1)) / m->beta;
+    m->lam2 = std::max(r2, 1e-3 * std::abs(m->a2)) / m->beta;
+
+    // device block: FP64 medium, FP32 medium, physical fields, axis tables
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t o_rb64 = take(sizeof(double) * D * N), o_q64 = take(sizeof(cx<double>) * N);
+    const size_t o_rb32 = take(sizeof(float) * D * N), o_q32 = take(sizeof(cx<float>) * N);
+    const size_t o_c = take(sizeof(double) * N), o_r = take(sizeof(double) * N), o_a = take(sizeof(double) * N);
+    size_t o_tab64[3][5], o_tab32[3][5];
+    for (int d = 0; d < 3; ++d) {
+        for (int t = 0; t < 3; ++t) o_tab64[d][t] = take(sizeof(double) * g.n[d]);
+        for (int t = 3; t < 5; ++t) o_tab64[d][t] = take(sizeof(cx<double>) * g.n[d]);
+        for (int t = 0; t < 3; ++t) o_tab32[d][t] = take(sizeof(float) * g.n[d]);
+        for (int t = 3; t < 5; ++t) o_tab32[d][t] = take(sizeof(cx<float>) * g.n[d]);
+    }
+    if (hipMalloc(&m->dev, off) != hipSuccess) {
+        delete m;
+        return CBS_E_NOMEM;
+    }
+    char* base = static_cast<char*>(m->dev);
+    m->rhobar64 = reinterpret_cast<double*>(base + o_rb64);
+    m->q64 = reinterpret_cast<cx<double>*>(base + o_q64);
+    m->rhobar32 = reinterpret_cast<float*>(base + o_rb32);
+    m->q32 = reinterpret_cast<cx<float>*>(base + o_q32);
+    m->c64 = reinterpret_cast<double*>(base + o_c);
+    m->rho64 = reinterpret_cast<double*>(base + o_r);
+    m->alpha64 = reinterpret_cast<double*>(base + o_a);
+
+    std::vector<char> host(off, 0);
+    auto hput = [&](size_t o, const void* src, size_t bytes) { std::memcpy(host.data() + o, src, bytes); };
+    hput(o_rb64, rb.data(), sizeof(double) * D * N);
+    {
+        std::vector<cx<double>> q64(N);
+        std::vector<cx<float>> q32(N);
+        std::vector<float> rb32((size_t)D * N);
+        for (int64_t i = 0; i < N; ++i) {
+            q64[i] = {q[i].real(), q[i].imag()};
+            q32[i] = {(float)q[i].real(), (float)q[i].imag()};
+        }
+        for (size_t i = 0; i < rb.size(); ++i) rb32[i] = (float)rb[i];
+        hput(o_q64, q64.data(), sizeof(cx<double>) * N);
+        hput(o_q32, q32.data(), sizeof(cx<float>) * N);
+        hput(o_rb32, rb32.data(), sizeof(float) * D * N);
+    }
+    hput(o_c, hc.data(), sizeof(double) * N);
+    hput(o_r, hr.data(), sizeof(double) * N);
+    hput(o_a, ha.data(), sizeof(double) * N);
+    for (int d = 0; d < 3; ++d) {
+        const int n = g.n[d];
+        std::vector<double> kv(n), tr(n), ti(n);
+        std::vector<cx<double>> sh(n), tw(n);
+        std::vector<float> kv32(n), gc32(n), gs32(n);
+        std::vector<cx<float>> sh32(n), tw32(n);
+        for (int j = 0; j < n; ++j) {
+            const int fidx = (j < (n + 1) / 2) ? j : j - n;   // FFT order
+            kv[j] = d < D ? 2.0 * M_PI * fidx / (n * dx) : 0.0;
+            sh[j] = {std::cos(kv[j] * dx / 2), std::sin(kv[j] * dx / 2)};
+            const double ang = -2.0 * M_PI * (double)j / (double)n;
+            tw[j] = {std::cos(ang), std::sin(ang)};
+            kv32[j] = (float)kv[j];
+            sh32[j] = {(float)sh[j].re, (float)sh[j].im};
+            tw32[j] = {(float)tw[j].re, (float)tw[j].im};
+            gc32[j] = (float)prof_c[d][j];
+            gs32[j] = (float)prof_s[d][j];
+        }
+        hput(o_tab64[d][0], prof_c[d].data(), sizeof(double) * n);
+        hput(o_tab64[d][1], prof_s[d].data(), sizeof(double) * n);
+        hput(o_tab64[d][2], kv.data(), sizeof(double) * n);
+        hput(o_tab64[d][3], sh.data(), sizeof(cx<double>) * n);
+        hput(o_tab64[d][4], tw.data(), sizeof(cx<double>) * n);
+        hput(o_tab32[d][0], gc32.data(), sizeof(float) * n);
+        hput(o_tab32[d][1], gs32.data(), sizeof(float) * n);
+        hput(o_tab32[d][2], kv32.data(), sizeof(float) * n);
+        hput(o_tab32[d][3], sh32.data(), sizeof(cx<float>) * n);
+        hput(o_tab32[d][4], tw32.data(), sizeof(cx<float>) * n);
+        m->gc64[d] = reinterpret_cast<double*>(base + o_tab64[d][0]);
+        m->gs64[d] = reinterpret_cast<double*>(base + o_tab64[d][1]);
+        m->kv64[d] = reinterpret_cast<double*>(base + o_tab64[d][2]);
+        m->sh64[d] = reinterpret_cast<cx<double>*>(base + o_tab64[d][3]);
+        m->tw64[d] = reinterpret_cast<cx<double>*>(base + o_tab64[d][4]);
+        m->gc32[d] = reinterpret_cast<float*>(base + o_tab32[d][0]);
+        m->gs32[d] = reinterpret_cast<float*>(base + o_tab32[d][1]);
+        m->kv32[d] = reinterpret_cast<float*>(base + o_tab32[d][2]);
+        m->sh32[d] = reinterpret_cast<cx<float>*>(base + o_tab32[d][3]);
+        m->tw32[d] = reinterpret_cast<cx<float>*>(base + o_tab32[d][4]);
+    }
+    if (hipMemcpyAsync(m->dev, host.data(), off, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipFree(m->dev);
+        delete m;
+        return CBS_E_DEVICE;
+    }
+    m->ps64 = make_passes(g, true);
+    m->ps32 = make_passes(g, false);
+    *out = m;
+    return CBS_OK;
+}
+
+cbs_status cbs_destroy_medium(cbs_medium m) {
+    if (!m) return CBS_E_INVALID;
+    if (m->dev) (void)hipFree(m->dev);
+    delete m;
+    return CBS_OK;
+}
+
+cbs_status cbs_medium_scalars(cbs_medium m, double out[8]) {
+    if (!m || !out) return CBS_E_INVALID;
+    out[0] = m->a1.real();
+    out[1] = m->a1.imag();
+    out[2] = m->a2.real();
+    out[3] = m->a2.imag();
+    out[4] = m->lam1;
+    out[5] = m->lam2;
+    out[6] = m->beta;
+    out[7] = m->nu;
+    return CBS_OK;
+}
+
+cbs_status cbs_set_scalars(cbs_medium m, const double in[6]) {
+    if (!m || !in) return CBS_E_INVALID;
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(in[i])) return CBS_E_INVALID;
+    if (!(in[4] > 0) || !(in[5] > 0)) return CBS_E_INVALID;
+    m->a1 = cd(in[0], in[1]);
+    m->a2 = cd(in[2], in[3]);
+    m->lam1 = in[4];
+    m->lam2 = in[5];
+    return CBS_OK;
+}
+
+cbs_status cbs_workspace_bytes(cbs_medium m, int32_t prec, int32_t batch, size_t* bytes) {
+    if (!m || !bytes || batch < 1) return CBS_E_INVALID;
+    if (prec != CBS_FP64 && prec != CBS_FP32_REFINED) return CBS_E_INVALID;
+    *bytes = layout_for(m, prec).total * (size_t)batch;
+    return CBS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Stage host or device sources into device complex128 arrays.  Host data is
+// copied into `stage` (at least (ndim + 1) * ncell complex128).
+cbs_status stage_sources(const cbs_medium_s* m, const void* s_p, const void* s_u, int ptr_kind, cx<double>* stage,
+                         const cx<double>** dsp, const cx<double>** dsu, hipStream_t st) {
+    const int64_t N = m->g.ncell;
+    const int D = m->g.ndim;
+    if (ptr_kind == CBS_PTR_DEVICE) {
+        *dsp = static_cast<const cx<double>*>(s_p);
+        *dsu = static_cast<const cx<double>*>(s_u);
+        return CBS_OK;
+    }
+    // stage layout: [u planes D*N][p N]
+    if (s_u) HIPOK(hipMemcpyAsync(stage, s_u, sizeof(cx<double>) * D * N, hipMemcpyHostToDevice, st));
+    HIPOK(hipMemcpyAsync(stage + (size_t)D * N, s_p, sizeof(cx<double>) * N, hipMemcpyHostToDevice, st));
+    HIPOK(hipStreamSynchronize(st));
+    *dsp = stage + (size_t)D * N;
+    *dsu = s_u ? stage : nullptr;
+    return CBS_OK;
+}
+
+// Write (u, p) = C^{-1/2} x to the caller's outputs.
+template <typename T>
+cbs_status write_outputs(const cbs_medium_s* m, const cx<T>* x, void* p_out, void* u_out, int ptr_kind,
+                         cx<double>* stage, hipStream_t st) {
+    const int64_t N = m->g.ncell;
+    const int D = m->g.ndim;
+    const double il1s = 1.0 / std::sqrt(m->lam1), il2s = 1.0 / std::sqrt(m->lam2);
+    if (ptr_kind == CBS_PTR_DEVICE) {
+        HIPOK(launch_unscale<T>(m->g, x, il1s, il2s, static_cast<cx<double>*>(p_out),
+                                static_cast<cx<double>*>(u_out), st));
+        HIPOK(hipStreamSynchronize(st));
+        return CBS_OK;
+    }
+    HIPOK(launch_unscale<T>(m->g, x, il1s, il2s, stage + (size_t)D * N, stage, st));
+    if (p_out) HIPOK(hipMemcpyAsync(p_out, stage + (size_t)D * N, sizeof(cx<double>) * N, hipMemcpyDeviceToHost, st));
+    if (u_out) HIPOK(hipMemcpyAsync(u_out, stage, sizeof(cx<double>) * D * N, hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    return CBS_OK;
+}
+
+cbs_status read_ctl(const Ctl* d, Ctl* h, hipStream_t st) {
+    HIPOK(hipMemcpyAsync(h, d, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    return CBS_OK;
+}
+
+cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* o, void* p_out,
+                      void* u_out, void* ws, size_t wsb, cbs_solve_info* info, void* hip_stream, int adjoint) {
+    const double t0 = now_s();
+    if (!m || !s_p || !o || !p_out || !ws) return CBS_E_INVALID;
+    if (o->prec != CBS_FP64 && o->prec != CBS_FP32_REFINED) return CBS_E_INVALID;
+    if (o->ptr_kind != CBS_PTR_HOST && o->ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    if (o->rhs_kind != CBS_RHS_PHYSICAL && o->rhs_kind != CBS_RHS_EQUATION) return CBS_E_INVALID;
+    if (!(o->tol >= 0) || o->max_iter < 1 || o->max_iter > 0x7fffffff) return CBS_E_INVALID;
+    const Layout L = layout_for(m, o->prec);
+    if (wsb < L.total) return CBS_E_NOMEM;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom& g = m->g;
+    const int64_t nf = (int64_t)(g.ndim + 1) * g.ncell;
+    const int check = o->check_every > 0 ? o->check_every : 32;
+
+    Slot<double>* dslot64 = at<Slot<double>>(ws, L.off_slot64);
+    Ctl* ctl64 = at<Ctl>(ws, L.off_ctl64);
+    cx<double>* x64 = at<cx<double>>(ws, L.off_x64);
+    cx<double>* w64 = at<cx<double>>(ws, L.off_w64);
+    cx<double>* y64 = at<cx<double>>(ws, L.off_y64);
+    double* part64 = at<double>(ws, L.off_part64);
+
+    // right-hand side y = C^{-1/2} s_hat (FP64)
+    const cx<double>*dsp = nullptr, *dsu = nullptr;
+    cbs_status cs = stage_sources(m, s_p, s_u, o->ptr_kind, w64, &dsp, &dsu, st);
+    if (cs != CBS_OK) return cs;
+    HIPOK(launch_rhs(g, dsp, dsu, m->rhobar64, m->q64, o->rhs_kind == CBS_RHS_PHYSICAL, 1.0 / std::sqrt(m->lam1),
+                     1.0 / std::sqrt(m->lam2), y64, nullptr, st));
+    HIPOK(launch_zero<double>(x64, nf, st));
+    HIPOK(hipMemsetAsync(ctl64, 0, sizeof(Ctl), st));
+    Slot<double> h64 = make_slot<double>(m, x64, w64, y64, ctl64, part64, adjoint);
+    HIPOK(hipMemcpyAsync(dslot64, &h64, sizeof(h64), hipMemcpyHostToDevice, st));
+
+    cbs_solve_info inf{};
+    inf.rel_residual = -1.0;
+    Ctl hc{};
+    int status = CBS_NOT_CONVERGED;
+
+    if (o->prec == CBS_FP64) {
+        const bool by_res = o->stop_rule == CBS_STOP_RESIDUAL;
+        HIPOK(launch_ctl_reset(ctl64, (int)o->max_iter, by_res ? -1.0 : o->tol, st));
+        int64_t launched = 0;
+        while (true) {
+            const int64_t chunk = std::min<int64_t>(check, o->max_iter - launched);
+            for (int64_t k = 0; k < chunk; ++k) HIPOK(run_passes<double>(m, m->ps64, MODE_CBS, dslot64, 1, st));
+            launched += chunk;
+            if (by_res) {
+                HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st));
+                inf.residual_evals++;
+            }
+            if ((cs = read_ctl(ctl64, &hc, st)) != CBS_OK) return cs;
+            inf.iterations = hc.iter;
+            inf.rel_update = hc.rel_update;
+            if (by_res) {
+                inf.rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
+                if (!std::isfinite(inf.rel_residual)) {
+                    status = CBS_E_DIVERGED;
+                    break;
+                }
+                if (inf.rel_residual <= o->tol) {
+                    status = CBS_OK;
+                    break;
+                }
+            }
+            if (hc.done == CONVERGED) {
+                status = CBS_OK;
+                break;
+            }
+            if (hc.done == DIVERGED) {
+                status = CBS_E_DIVERGED;
+                break;
+            }
+            if (hc.done == CAPPED || launched >= o->max_iter) {
+                status = CBS_NOT_CONVERGED;
+                break;
+            }
+        }
+        if (status != CBS_E_DIVERGED) {
+            cs = write_outputs<double>(m, x64, p_out, u_out, o->ptr_kind, w64, st);
+            if (cs != CBS_OK) return cs;
+        }
+    } else {
+        // FP32 inner CBS with FP64 residual and accumulation
+        Slot<float>* dslot32 = at<Slot<float>>(ws, L.off_slot32);
+        Ctl* ctl32 = at<Ctl>(ws, L.off_ctl32);
+        cx<float>* d32 = at<cx<float>>(ws, L.off_d32);
+        cx<float>* w32 = at<cx<float>>(ws, L.off_w32);
+        cx<float>* y32 = at<cx<float>>(ws, L.off_y32);
+        double* part32 = at<double>(ws, L.off_part32);
+        HIPOK(hipMemsetAsync(ctl32, 0, sizeof(Ctl), st));
+        Slot<float> h32 = make_slot<float>(m, d32, w32, y32, ctl32, part32, adjoint);
+        HIPOK(hipMemcpyAsync(dslot32, &h32, sizeof(h32), hipMemcpyHostToDevice, st));
+        const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
+        const int max_outer = o->max_outer > 0 ? o->max_outer : 50;
+        // x64 = 0 so the first residual is y: evaluate it with the APPLY passes
+        int64_t total = 0;
+        for (int outer = 0;; ++outer) {
+            HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st));
+            inf.residual_evals++;
+            if ((cs = read_ctl(ctl64, &hc, st)) != CBS_OK) return cs;
+            inf.rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
+            inf.outer = outer;
+            if (!std::isfinite(inf.rel_residual)) {
+                status = CBS_E_DIVERGED;
+                break;
+            }
+            if (inf.rel_residual <= o->tol) {
+                status = CBS_OK;
+                break;
+            }
+            if (outer >= max_outer || total >= o->max_iter) {
+                status = CBS_NOT_CONVERGED;
+                break;
+            }
+            HIPOK(launch_convert(w64, y32, nf, ctl64, st));
+            HIPOK(launch_zero<float>(d32, nf, st));
+            const int64_t cap = o->max_iter - total;
+            HIPOK(launch_ctl_reset(ctl32, (int)cap, inner_tol, st));
+            Ctl ic{};
+            int64_t launched = 0;
+            while (true) {
+                const int64_t chunk = std::min<int64_t>(check, cap - launched);
+                for (int64_t k = 0; k < chunk; ++k) HIPOK(run_passes<float>(m, m->ps32, MODE_CBS, dslot32, 1, st));
+                launched += chunk;
+                if ((cs = read_ctl(ctl32, &ic, st)) != CBS_OK) return cs;
+                if (ic.done != RUNNING || launched >= cap) break;
+            }
+            total += ic.iter;
+            inf.rel_update = ic.rel_update;
+            if (ic.done == DIVERGED) {
+                status = CBS_E_DIVERGED;
+                break;
+            }
+            HIPOK(launch_accumulate(x64, d32, nf, ctl64, st));
+        }
+        inf.iterations = total;
+        if (status != CBS_E_DIVERGED) {
+            cs = write_outputs<double>(m, x64, p_out, u_out, o->ptr_kind, w64, st);
+            if (cs != CBS_OK) return cs;
+        }
+    }
+    inf.status = status;
+    inf.seconds = now_s() - t0;
+    if (info) *info = inf;
+    return (cbs_status)status;
+}
+
+}  // namespace
+
+extern "C" {
+
+cbs_status cbs_solve(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts, void* p_out,
+                     void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info, void* hip_stream) {
+    return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 0);
+}
+
+cbs_status cbs_solve_adjoint(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts,
+                             void* p_out, void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info,
+                             void* hip_stream) {
+    return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 1);
+}
+
+cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,
+                        int32_t adjoint, int32_t rhs_kind, int32_t ptr_kind, double* rel_residual, void* r_p,
+                        void* r_u, void* workspace, size_t ws_bytes, void* hip_stream) {
+    if (!m || !s_p || !p || !workspace) return CBS_E_INVALID;
+    if (ptr_kind != CBS_PTR_HOST && ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    if (rhs_kind != CBS_RHS_PHYSICAL && rhs_kind != CBS_RHS_EQUATION) return CBS_E_INVALID;
+    const Layout L = layout_for(m, CBS_FP64);
+    if (ws_bytes < L.total) return CBS_E_NOMEM;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom& g = m->g;
+    const int64_t N = g.ncell;
+    const int D = g.ndim;
+    Slot<double>* dslot = at<Slot<double>>(workspace, L.off_slot64);
+    Ctl* ctl = at<Ctl>(workspace, L.off_ctl64);
+    cx<double>* x = at<cx<double>>(workspace, L.off_x64);
+    cx<double>* w = at<cx<double>>(workspace, L.off_w64);
+    cx<double>* y = at<cx<double>>(workspace, L.off_y64);
+    double* part = at<double>(workspace, L.off_part64);
+    // sources -> y (staged through w), fields -> x (staged through w)
+    const cx<double>*dsp = nullptr, *dsu = nullptr;
+    cbs_status cs = stage_sources(m, s_p, s_u, ptr_kind, w, &dsp, &dsu, st);
+    if (cs != CBS_OK) return cs;
+    HIPOK(launch_rhs(g, dsp, dsu, m->rhobar64, m->q64, rhs_kind == CBS_RHS_PHYSICAL, 1.0 / std::sqrt(m->lam1),
+                     1.0 / std::sqrt(m->lam2), y, nullptr, st));
+    const cx<double>*dp = nullptr, *du = nullptr;
+    cs = stage_sources(m, p, u, ptr_kind, w, &dp, &du, st);
+    if (cs != CBS_OK) return cs;
+    HIPOK(launch_scale_in(g, dp, du, std::sqrt(m->lam1), std::sqrt(m->lam2), x, st));
+    HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+    Slot<double> h = make_slot<double>(m, x, w, y, ctl, part, adjoint ? 1 : 0);
+    HIPOK(hipMemcpyAsync(dslot, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot, 1, st));
+    Ctl hc{};
+    if ((cs = read_ctl(ctl, &hc, st)) != CBS_OK) return cs;
+    if (rel_residual) *rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
+    if (r_p || r_u) {
+        const double sl1 = std::sqrt(m->lam1), sl2 = std::sqrt(m->lam2);
+        if (ptr_kind == CBS_PTR_DEVICE) {
+            HIPOK(launch_residual_out(g, w, sl1, sl2, static_cast<cx<double>*>(r_p), static_cast<cx<double>*>(r_u),
+                                      st));
+        } else {
+            // x is free now: use it as the staging area
+            HIPOK(launch_residual_out(g, w, sl1, sl2, x + (size_t)D * N, x, st));
+            if (r_p) HIPOK(hipMemcpyAsync(r_p, x + (size_t)D * N, sizeof(cx<double>) * N, hipMemcpyDeviceToHost, st));
+            if (r_u) HIPOK(hipMemcpyAsync(r_u, x, sizeof(cx<double>) * D * N, hipMemcpyDeviceToHost, st));
+        }
+        HIPOK(hipStreamSynchronize(st));
+    }
+    return CBS_OK;
+}
+
+cbs_status cbs_gradient(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,
+                        const void* lp, const void* lu, int32_t ptr_kind, double* g_c, double* g_rho,
+                        double* g_alpha, void* hip_stream) {
+    if (!m || !s_p || !p || !lp) return CBS_E_INVALID;
+    if (ptr_kind != CBS_PTR_HOST && ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom& g = m->g;
+    const int64_t N = g.ncell;
+    const int D = g.ndim;
+    const double* gcen[3] = {m->gc64[0], m->gc64[1], m->gc64[2]};
+    const double* gst[3] = {m->gs64[0], m->gs64[1], m->gs64[2]};
+    if (ptr_kind == CBS_PTR_DEVICE) {
+        HIPOK(launch_gradient(g, m->c64, m->rho64, m->alpha64, m->q64, gcen, gst, m->gmax, m->grid.omega,
+                              static_cast<const cx<double>*>(s_p), static_cast<const cx<double>*>(s_u),
+                              static_cast<const cx<double>*>(p), static_cast<const cx<double>*>(u),
+                              static_cast<const cx<double>*>(lp), static_cast<const cx<double>*>(lu), g_c, g_rho,
+                              g_alpha, st));
+        HIPOK(hipStreamSynchronize(st));
+        return CBS_OK;
+    }
+    // host pointers: stage everything through one temporary device block
+    const size_t cN = sizeof(cx<double>) * N, rN = sizeof(double) * N;
+    const size_t bytes = 3 * cN + 3 * (size_t)D * cN + 3 * rN;
+    char* tmp = nullptr;
+    if (hipMalloc(&tmp, bytes) != hipSuccess) return CBS_E_NOMEM;
+    cx<double>* dsp = reinterpret_cast<cx<double>*>(tmp);
+    cx<double>* dp = dsp + N;
+    cx<double>* dlp = dp + N;
+    cx<double>* dsu = dlp + N;
+    cx<double>* du = dsu + (size_t)D * N;
+    cx<double>* dlu = du + (size_t)D * N;
+    double* dgc = reinterpret_cast<double*>(dlu + (size_t)D * N);
+    double* dgr = dgc + N;
+    double* dga = dgr + N;
+    cbs_status rc = CBS_OK;
+    auto h2d = [&](void* dst, const void* src, size_t b) {
+        if (src && hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, st) != hipSuccess) rc = CBS_E_DEVICE;
+    };
+    h2d(dsp, s_p, cN);
+    h2d(dp, p, cN);
+    h2d(dlp, lp, cN);
+    h2d(dsu, s_u, D * cN);
+    h2d(du, u, D * cN);
+    h2d(dlu, lu, D * cN);
+    if (rc == CBS_OK &&
+        launch_gradient(g, m->c64, m->rho64, m->alpha64, m->q64, gcen, gst, m->gmax, m->grid.omega, dsp,
+                        s_u ? dsu : nullptr, dp, u ? du : nullptr, dlp, lu ? dlu : nullptr, dgc, dgr, dga,
+                        st) != hipSuccess)
+        rc = CBS_E_DEVICE;
+    if (rc == CBS_OK) {
+        if (g_c && hipMemcpyAsync(g_c, dgc, rN, hipMemcpyDeviceToHost, st) != hipSuccess) rc = CBS_E_DEVICE;
+        if (g_rho && hipMemcpyAsync(g_rho, dgr, rN, hipMemcpyDeviceToHost, st) != hipSuccess) rc = CBS_E_DEVICE;
+        if (g_alpha && hipMemcpyAsync(g_alpha, dga, rN, hipMemcpyDeviceToHost, st) != hipSuccess)
+            rc = CBS_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) rc = CBS_E_DEVICE;
+    (void)hipFree(tmp);
+    return rc;
+}
+
+// batched slots: implemented in cbs_batch.cpp
+}  // extern "C"

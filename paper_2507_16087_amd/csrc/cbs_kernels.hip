@@ -1,0 +1,1009 @@
+// gfx950 kernels of the iterative Born solver (arXiv 2507.16087, Algorithm 1
+// on the staggered first-order system of App. B.1).
+//
+// One CBS iteration (eq. BornAlt: x <- x + nu B [(L+I)^{-1}(B x + y) - x]) on
+// an n0 x n1 x n2 grid with F = ndim + 1 complex fields runs as five passes
+// over HBM, each a batch of 1-D FFTs along one axis:
+//   pass A  axis 2 (contiguous): w = B x + y fused into the load, forward FFT
+//   pass B  axis 1 (strided)   : forward FFT                        (3-D only)
+//   pass C  axis 0 (strided)   : forward FFT, (L+I)^{-1} per wavevector with
+//                                all F fields in registers, inverse FFT
+//   pass D  axis 1 (strided)   : inverse FFT                        (3-D only)
+//   pass E  axis 2 (contiguous): inverse FFT, x += nu B (z - x) and the
+//                                |dx|^2, |x|^2 partial sums fused into the store
+// followed by a one-block-per-slot reduction that advances the iteration
+// counter and raises the slot's stop flag.  The same passes with a different
+// middle operator (i k S / sqrt(lam1 lam2)) and epilogue (r = y - D x / lam - z)
+// evaluate the scaled true residual y - (L+V) x used by iterative refinement.
+//
+// FFTs are Stockham radix-R stages (R in 2..16, including 3, 6, 12): every
+// thread owns whole butterflies, the first stage of a strided pass loads
+// straight from HBM (columns of P adjacent cells give coalesced row segments),
+// stages exchange through an LDS tile, and the last stage stores straight to
+// HBM in natural order.  Contiguous passes stage the P-pencil tile through LDS
+// with a fully coalesced copy so the fused prologue / epilogue read and write
+// whole cache lines.  The middle pass keeps the forward spectrum in registers
+// and starts the inverse transform from them (reversed radix order), so the
+// propagator costs no extra LDS or HBM traffic.
+#include "cbs_internal.h"
+
+#include <utility>
+
+namespace cbs {
+
+// ---------------------------------------------------------------- complex --
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {   // a * conj(b)
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> rmul(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.im, a.re}; }   // i a
+template <typename T>
+__device__ __forceinline__ cx<T> cinv(cx<T> a) {
+    T d = T(1) / (a.re * a.re + a.im * a.im);
+    return {a.re * d, -a.im * d};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// ------------------------------------------------ compile-time twiddles --
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+    double term = x, sum = x;
+    for (int i = 1; i < 24; ++i) {
+        term *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int i = 1; i < 24; ++i) {
+        term *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double red_angle(int m, int R) {
+    double a = 2.0 * kPi * (double)m / (double)R;
+    return a > kPi ? a - 2.0 * kPi : a;
+}
+
+template <int... I, typename F>
+__device__ __forceinline__ void sfor_(std::integer_sequence<int, I...>, F&& f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    sfor_(std::make_integer_sequence<int, N>{}, static_cast<F&&>(f));
+}
+
+// v * exp(DIR 2 pi i M / R), exact for multiples of a quarter turn
+template <int M, int R, int DIR, typename T>
+__device__ __forceinline__ cx<T> twc(cx<T> v) {
+    constexpr int m = ((M % R) + R) % R;
+    if constexpr (m == 0) {
+        return v;
+    } else if constexpr ((4 * m) % R == 0) {
+        constexpr int q = (4 * m) / R;
+        if constexpr (q == 2) return {-v.re, -v.im};
+        else if constexpr ((q == 1) == (DIR > 0)) return {-v.im, v.re};
+        else return {v.im, -v.re};
+    } else {
+        constexpr T c = (T)taylor_cos(red_angle(m, R));
+        constexpr T s = (T)(DIR * taylor_sin(red_angle(m, R)));
+        return {v.re * c - v.im * s, v.re * s + v.im * c};
+    }
+}
+
+// ---------------------------------------------------- in-register DFTs --
+// X_k = sum_n x_n exp(DIR 2 pi i n k / R), in place, natural order.
+template <int R, int DIR>
+struct Dft {
+    static constexpr int R1 = (R % 4 == 0) ? 4 : ((R % 3 == 0) ? 3 : 2);
+    static constexpr int R2 = R / R1;
+    template <typename T>
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        // R = R1 * R2: R2 DFTs of length R1 over n1 (stride R2), twiddle,
+        // R1 DFTs of length R2 over n2; output index k1 + R1 k2.
+        cx<T> t[R];
+        sfor<R2>([&](auto N2) {
+            constexpr int n2 = decltype(N2)::value;
+            cx<T> a[R1];
+            sfor<R1>([&](auto N1) { a[decltype(N1)::value] = v[n2 + R2 * decltype(N1)::value]; });
+            Dft<R1, DIR>::run(a);
+            sfor<R1>([&](auto K1) {
+                constexpr int k1 = decltype(K1)::value;
+                t[n2 * R1 + k1] = twc<n2 * k1, R, DIR>(a[k1]);
+            });
+        });
+        sfor<R1>([&](auto K1) {
+            constexpr int k1 = decltype(K1)::value;
+            cx<T> b[R2];
+            sfor<R2>([&](auto N2) { b[decltype(N2)::value] = t[decltype(N2)::value * R1 + k1]; });
+            Dft<R2, DIR>::run(b);
+            sfor<R2>([&](auto K2) { v[k1 + R1 * decltype(K2)::value] = b[decltype(K2)::value]; });
+        });
+    }
+};
+template <int DIR>
+struct Dft<1, DIR> {
+    template <typename T>
+    __device__ __forceinline__ static void run(cx<T>*) {}
+};
+template <int DIR>
+struct Dft<2, DIR> {
+    template <typename T>
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        cx<T> a = v[0];
+        v[0] = a + v[1];
+        v[1] = a - v[1];
+    }
+};
+template <int DIR>
+struct Dft<3, DIR> {
+    template <typename T>
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        constexpr T h = (T)0.5;
+        constexpr T s = (T)(DIR * 0.86602540378443864676372317075293618);
+        cx<T> t = v[1] + v[2];
+        cx<T> m = {v[0].re - h * t.re, v[0].im - h * t.im};
+        cx<T> d = v[1] - v[2];
+        cx<T> e = {-s * d.im, s * d.re};   // i s (v1 - v2)
+        v[0] = v[0] + t;
+        v[1] = m + e;
+        v[2] = m - e;
+    }
+};
+template <int DIR>
+struct Dft<4, DIR> {
+    template <typename T>
+    __device__ __forceinline__ static void run(cx<T>* v) {
+        cx<T> a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], d = v[1] - v[3];
+        cx<T> e = (DIR > 0) ? cx<T>{-d.im, d.re} : cx<T>{d.im, -d.re};   // DIR i d
+        v[0] = a + c;
+        v[2] = a - c;
+        v[1] = b + e;
+        v[3] = b - e;
+    }
+};
+
+// ------------------------------------------------------------- FFT plans --
+// N = R0 R1 R2 points; TPC threads cooperate on one column, each owning
+// E = N / TPC elements (N / (R TPC) butterflies of every stage).
+template <int N_, int R0_, int R1_, int R2_, int TPC_>
+struct Plan {
+    static constexpr int N = N_, R0 = R0_, R1 = R1_, R2 = R2_, TPC = TPC_;
+    static constexpr int S = (R2 > 1) ? 3 : ((R1 > 1) ? 2 : 1);
+    static constexpr int E = N / TPC;
+    static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
+    static constexpr int radix(int s) { return s == 0 ? R0 : (s == 1 ? R1 : R2); }
+};
+
+// Stage s in execution order: forward runs R0, R1, R2; inverse runs them
+// reversed so it can start from the forward transform's last-stage registers.
+template <class P, int DIR>
+struct Seq {
+    static constexpr int r(int s) { return DIR < 0 ? P::radix(s) : P::radix(P::S - 1 - s); }
+    static constexpr int ns(int s) {
+        int a = 1;
+        for (int i = 0; i < s; ++i) a *= r(i);
+        return a;
+    }
+};
+
+// LDS tile: element n of column c at lds[n * ldp + c].
+template <int N, int R, int TPC, typename T>
+__device__ __forceinline__ void lds_gather(cx<T>* v, const cx<T>* lds, int ldp, int col, int lane) {
+    constexpr int NB = N / (R * TPC);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b * R + r] = lds[(lane + b * TPC + r * (N / R)) * ldp + col];
+}
+
+template <int N, int R, int Ns, int TPC, typename T>
+__device__ __forceinline__ void lds_scatter(const cx<T>* v, cx<T>* lds, int ldp, int col, int lane) {
+    constexpr int NB = N / (R * TPC);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = lane + b * TPC;
+        const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ldp + col] = v[b * R + r];
+    }
+}
+
+// Twiddle (stages after the first) and radix-R DFT on this thread's butterflies.
+template <int N, int R, int Ns, int TPC, int DIR, typename T>
+__device__ __forceinline__ void stage_compute(cx<T>* v, int lane, const cx<T>* __restrict__ tw) {
+    constexpr int NB = N / (R * TPC);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if constexpr (Ns > 1) {
+            const int jm = (lane + b * TPC) % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[jm * r * (N / (Ns * R))];
+                v[b * R + r] = (DIR < 0) ? cmul(v[b * R + r], w) : cmulc(v[b * R + r], w);
+            }
+        }
+        Dft<R, DIR>::run(&v[b * R]);
+    }
+}
+
+// Full transform of one column.  On entry v holds the first stage's inputs
+// (elements lane + b TPC + r N/R); on exit v holds the outputs of the last
+// stage, element lane + b TPC + r N/R_last in natural order.  The LDS tile
+// must be free on entry; it is still being read on exit.
+template <class P, int DIR, typename T>
+__device__ __forceinline__ void fft_regs(cx<T>* v, cx<T>* lds, int ldp, int col, int lane,
+                                         const cx<T>* __restrict__ tw) {
+    using Q = Seq<P, DIR>;
+    constexpr int N = P::N, TPC = P::TPC;
+    stage_compute<N, Q::r(0), 1, TPC, DIR>(v, lane, tw);
+    if constexpr (P::S >= 2) {
+        lds_scatter<N, Q::r(0), 1, TPC>(v, lds, ldp, col, lane);
+        __syncthreads();
+        lds_gather<N, Q::r(1), TPC>(v, lds, ldp, col, lane);
+        stage_compute<N, Q::r(1), Q::ns(1), TPC, DIR>(v, lane, tw);
+    }
+    if constexpr (P::S >= 3) {
+        __syncthreads();
+        lds_scatter<N, Q::r(1), Q::ns(1), TPC>(v, lds, ldp, col, lane);
+        __syncthreads();
+        lds_gather<N, Q::r(2), TPC>(v, lds, ldp, col, lane);
+        stage_compute<N, Q::r(2), Q::ns(2), TPC, DIR>(v, lane, tw);
+    }
+}
+
+// Index of element (lane, b, r) of the last stage in natural order.
+template <class P, int DIR>
+__device__ __forceinline__ int out_index(int lane, int b, int r) {
+    constexpr int Rl = Seq<P, DIR>::r(P::S - 1);
+    return lane + b * P::TPC + r * (P::N / Rl);
+}
+template <class P, int DIR>
+__device__ __forceinline__ int in_index(int lane, int b, int r) {
+    constexpr int R0 = Seq<P, DIR>::r(0);
+    return lane + b * P::TPC + r * (P::N / R0);
+}
+
+// ------------------------------------------------- medium on the fly --
+// Diagonal of the row-scaled staggered system at one cell, conjugated for
+// the adjoint: D_u_eta = rhobar_eta (gamma_eta + i w), D_p = (gamma + i w) q,
+// with gamma = gmax sum_d r_d^2 (staggered point for the velocity row eta).
+template <typename T>
+__device__ __forceinline__ cx<T> diag_D(const Slot<T>& s, const Geom& g, int f, int64_t cell,
+                                        const int* ix) {
+    T gsum = 0;
+    for (int d = 0; d < g.ndim; ++d) gsum += (d == f) ? s.gs[d][ix[d]] : s.gc[d][ix[d]];
+    const T gam = s.gmax * gsum;
+    cx<T> D;
+    if (f < g.ndim) {
+        const T rb = s.rhobar[(int64_t)f * g.ncell + cell];
+        D = {rb * gam, rb * s.omega};
+    } else {
+        const cx<T> q = s.q[cell];
+        D = {gam * q.re - s.omega * q.im, gam * q.im + s.omega * q.re};
+    }
+    if (s.adjoint) D.im = -D.im;
+    return D;
+}
+
+// B = I - V, V = (D - a) / lam (eq. LV), conjugated for the adjoint.
+template <typename T>
+__device__ __forceinline__ cx<T> bval(const Slot<T>& s, const Geom& g, int f, int64_t cell,
+                                      const int* ix) {
+    const cx<T> D = diag_D(s, g, f, cell, ix);
+    const bool u = f < g.ndim;
+    const T are = u ? s.a1re : s.a2re;
+    const T aim = s.adjoint ? -(u ? s.a1im : s.a2im) : (u ? s.a1im : s.a2im);
+    const T il = u ? s.inv_lam1 : s.inv_lam2;
+    return {T(1) - (D.re - are) * il, -(D.im - aim) * il};
+}
+
+// Coordinates of element e of a contiguous tile (pencil = tile pencil0 + e / N).
+template <int N>
+__device__ __forceinline__ void tile_coords(const Geom& g, int pencil0, int e, int* ix) {
+    const int pencil = pencil0 + e / N;
+    if (g.ndim == 3) {
+        ix[2] = e % N;
+        ix[1] = pencil % g.n[1];
+        ix[0] = pencil / g.n[1];
+    } else {
+        ix[1] = e % N;
+        ix[0] = pencil;
+        ix[2] = 0;
+    }
+}
+
+__device__ __forceinline__ void cell_coords(const Geom& g, int64_t cell, int* ix) {
+    int64_t r = cell;
+    for (int d = g.ndim - 1; d >= 0; --d) {
+        ix[d] = (int)(r % g.n[d]);
+        r /= g.n[d];
+    }
+}
+
+// ---------------------------------------------------------- pass modes --
+enum Mode { CBS = 0, APPLY = 1 };
+
+// Block reduction of two doubles; thread 0 gets the totals.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[2 * wid] = a;
+        red[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < nw; ++i) {
+            a += red[2 * i];
+            b += red[2 * i + 1];
+        }
+    }
+}
+
+// ------------------------------------------- pass A / E: contiguous axis --
+// Tile = P consecutive pencils along the last axis (one contiguous run of
+// P * N cells).  grid = (tiles, F, slots); block = P * TPC threads.
+// FIRST: prologue (CBS: w = B x + y; APPLY: w = x), forward FFT, store w.
+// !FIRST: load w, inverse FFT, epilogue (CBS: x += nu B (z - x) with norm
+// partials; APPLY: w = y - D x / lam - z with |r|^2, |y|^2 partials).
+template <class P, int MODE, bool FIRST, typename T>
+__global__ void __launch_bounds__(256) k_contig(const Slot<T>* __restrict__ slots, Geom g, int pcols,
+                                                int ldp) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const Slot<T>& s = slots[blockIdx.z];
+    if (MODE == CBS && s.ctl->done) return;
+    constexpr int N = P::N;
+    const int f = blockIdx.y;
+    const int nthr = pcols * P::TPC;
+    const int tid = threadIdx.x;
+    const int64_t tile0 = (int64_t)blockIdx.x * pcols * N;     // first cell of the tile
+    const int64_t plane = (int64_t)f * g.ncell;
+    const int tile_elems = pcols * N;
+    const int last = g.ndim - 1;
+    const cx<T>* __restrict__ tw = s.tw[last];
+
+    if constexpr (FIRST) {
+        for (int e = tid; e < tile_elems; e += nthr) {
+            const int64_t cell = tile0 + e;
+            cx<T> xv = s.x[plane + cell];
+            cx<T> wv;
+            if constexpr (MODE == CBS) {
+                int ix[3];
+                tile_coords<N>(g, blockIdx.x * pcols, e, ix);
+                wv = cmul(bval(s, g, f, cell, ix), xv) + s.y[plane + cell];
+            } else {
+                wv = xv;
+            }
+            lds[(e % N) * ldp + e / N] = wv;
+        }
+    } else {
+        for (int e = tid; e < tile_elems; e += nthr) lds[(e % N) * ldp + e / N] = s.w[plane + tile0 + e];
+    }
+    __syncthreads();
+
+    const int col = tid % pcols, lane = tid / pcols;
+    constexpr int DIR = FIRST ? -1 : 1;
+    using Q = Seq<P, DIR>;
+    cx<T> v[P::E];
+    lds_gather<N, Q::r(0), P::TPC>(v, lds, ldp, col, lane);
+    __syncthreads();
+    fft_regs<P, DIR>(v, lds, ldp, col, lane, tw);
+    __syncthreads();
+    lds_scatter<N, Q::r(P::S - 1), Q::ns(P::S - 1), P::TPC>(v, lds, ldp, col, lane);
+    __syncthreads();
+
+    if constexpr (FIRST) {
+        for (int e = tid; e < tile_elems; e += nthr) s.w[plane + tile0 + e] = lds[(e % N) * ldp + e / N];
+    } else {
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int e = tid; e < tile_elems; e += nthr) {
+            const int64_t cell = tile0 + e;
+            const cx<T> z = lds[(e % N) * ldp + e / N];
+            int ix[3];
+            tile_coords<N>(g, blockIdx.x * pcols, e, ix);
+            if constexpr (MODE == CBS) {
+                const cx<T> xv = s.x[plane + cell];
+                const cx<T> b = bval(s, g, f, cell, ix);
+                const cx<T> dxv = rmul(s.nu, cmul(b, z - xv));
+                s.x[plane + cell] = xv + dxv;
+                acc0 += (double)norm2(dxv);
+                acc1 += (double)norm2(xv);
+            } else {
+                const cx<T> xv = s.x[plane + cell];
+                const cx<T> yv = s.y[plane + cell];
+                const cx<T> D = diag_D(s, g, f, cell, ix);
+                const T il = f < g.ndim ? s.inv_lam1 : s.inv_lam2;
+                const cx<T> r = yv - rmul(il, cmul(D, xv)) - z;
+                s.w[plane + cell] = r;
+                acc0 += (double)norm2(r);
+                acc1 += (double)norm2(yv);
+            }
+        }
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(smem_raw);
+        block_sum2(acc0, acc1, red);
+        if (tid == 0) {
+            const int64_t part = (int64_t)f * gridDim.x + blockIdx.x;
+            s.partials[2 * part] = acc0;
+            s.partials[2 * part + 1] = acc1;
+        }
+    }
+}
+
+// ------------------------------------------- pass B / D: strided axis --
+// FFT along axis `axis` (< ndim - 1) of the w buffer, in place.  Tile = P
+// adjacent columns along the last axis; the first stage loads straight from
+// HBM and the last stage stores straight to HBM.
+template <class P, int DIR, typename T>
+__global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slots, Geom g, int axis,
+                                                 int pcols, int ldp, int64_t es, int64_t ostride,
+                                                 int nlast_tiles, int skip_done) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const Slot<T>& s = slots[blockIdx.z];
+    if (skip_done && s.ctl->done) return;
+    const int tid = threadIdx.x;
+    const int col = tid % pcols, lane = tid / pcols;
+    const int64_t base = (int64_t)blockIdx.y * g.ncell + (int64_t)(blockIdx.x / nlast_tiles) * ostride +
+                         (int64_t)(blockIdx.x % nlast_tiles) * pcols + col;
+    cx<T>* __restrict__ w = s.w;
+    cx<T> v[P::E];
+    constexpr int NB0 = P::N / (Seq<P, DIR>::r(0) * P::TPC);
+#pragma unroll
+    for (int b = 0; b < NB0; ++b)
+#pragma unroll
+        for (int r = 0; r < Seq<P, DIR>::r(0); ++r)
+            v[b * Seq<P, DIR>::r(0) + r] = w[base + (int64_t)in_index<P, DIR>(lane, b, r) * es];
+    fft_regs<P, DIR>(v, lds, ldp, col, lane, s.tw[axis]);
+    constexpr int Rl = Seq<P, DIR>::r(P::S - 1);
+    constexpr int NBl = P::N / (Rl * P::TPC);
+#pragma unroll
+    for (int b = 0; b < NBl; ++b)
+#pragma unroll
+        for (int r = 0; r < Rl; ++r) w[base + (int64_t)out_index<P, DIR>(lane, b, r) * es] = v[b * Rl + r];
+}
+
+// ------------------------------------- pass C: axis 0 with the propagator --
+// Forward FFT of all F fields along axis 0, per-wavevector operator, inverse
+// FFT.  MODE CBS applies (L+I)^{-1} of App. B.1 (rank-one form, conjugate
+// transpose for the adjoint); MODE APPLY applies the scaled staggered
+// derivative block of L (negated for the adjoint).  1/prod(n) is folded in.
+template <class P, int MODE, typename T>
+__global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols,
+                                              int ldp, int64_t es, int64_t ostride, int nlast_tiles) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const Slot<T>& s = slots[blockIdx.z];
+    if (MODE == CBS && s.ctl->done) return;
+    constexpr int N = P::N, E = P::E;
+    const int D = g.ndim, F = D + 1;
+    const int tid = threadIdx.x;
+    const int col = tid % pcols, lane = tid / pcols;
+    const int io = blockIdx.x / nlast_tiles;                       // index along the middle axis (3-D)
+    const int il = (blockIdx.x % nlast_tiles) * pcols + col;       // index along the last axis
+    const int64_t base = (int64_t)io * ostride + il;
+    cx<T>* __restrict__ w = s.w;
+    const cx<T>* __restrict__ tw = s.tw[0];
+
+    // wavevector components of this column (axes 1.., FFT order)
+    T kc[2];
+    cx<T> gc[2];   // k S for the column axes
+    if (D == 3) {
+        kc[0] = s.kv[1][io];
+        gc[0] = rmul(kc[0], s.sh[1][io]);
+        kc[1] = s.kv[2][il];
+        gc[1] = rmul(kc[1], s.sh[2][il]);
+    } else {
+        kc[0] = s.kv[1][il];
+        gc[0] = rmul(kc[0], s.sh[1][il]);
+        kc[1] = 0;
+        gc[1] = {0, 0};
+    }
+
+    cx<T> v[4][E];
+    using QF = Seq<P, -1>;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (f < F) {
+            const int64_t pb = (int64_t)f * g.ncell + base;
+            constexpr int R0 = QF::r(0);
+#pragma unroll
+            for (int b = 0; b < N / (R0 * P::TPC); ++b)
+#pragma unroll
+                for (int r = 0; r < R0; ++r)
+                    v[f][b * R0 + r] = w[pb + (int64_t)in_index<P, -1>(lane, b, r) * es];
+            if (f > 0) __syncthreads();
+            fft_regs<P, -1>(v[f], lds, ldp, col, lane, tw);
+        }
+    }
+
+    // per-wavevector operator on the registers
+    constexpr int Rl = QF::r(P::S - 1);
+    const T sig = s.adjoint ? T(-1) : T(1);
+#pragma unroll
+    for (int b = 0; b < N / (Rl * P::TPC); ++b) {
+#pragma unroll
+        for (int r = 0; r < Rl; ++r) {
+            const int k0i = out_index<P, -1>(lane, b, r);
+            const int e = b * Rl + r;
+            const T k0 = s.kv[0][k0i];
+            const cx<T> g0 = rmul(k0, s.sh[0][k0i]);
+            cx<T> gg[3] = {g0, gc[0], gc[1]};
+            const cx<T> wp = (D == 3) ? v[3][e] : v[2][e];
+            // t = sum_eta conj(k_eta S_eta) w_eta
+            cx<T> t = cmulc(v[0][e], gg[0]);
+            t = t + cmulc(v[1][e], gg[1]);
+            if (D == 3) t = t + cmulc(v[2][e], gg[2]);
+            if constexpr (MODE == CBS) {
+                const T kk = k0 * k0 + kc[0] * kc[0] + kc[1] * kc[1];
+                cx<T> mu = {kk + s.al12.re, s.adjoint ? -s.al12.im : s.al12.im};
+                cx<T> imu = rmul(s.inv_ntot, cinv(mu));
+                const cx<T> ca = s.adjoint ? conjg(s.ca) : s.ca;
+                const cx<T> cp = s.adjoint ? conjg(s.cp) : s.cp;
+                // u_eta: ca (w_eta - g_eta t / mu) - i sig s g_eta wp / mu
+                const cx<T> tm = cmul(t, imu);
+                const cx<T> pm = rmul(sig * s.s, mul_i(cmul(wp, imu)));
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (d < D) {
+                        const cx<T> a = rmul(s.inv_ntot, v[d][e]) - cmul(gg[d], tm);
+                        v[d][e] = cmul(ca, a) - cmul(gg[d], pm);
+                    }
+                }
+                // p: -i sig s t / mu + cp wp / mu
+                const cx<T> pz = cmul(cp, cmul(wp, imu)) - rmul(sig * s.s, mul_i(tm));
+                if (D == 3) v[3][e] = pz;
+                else v[2][e] = pz;
+            } else {
+                // (L - diag) x in scaled form: u_eta = i sig g_eta p / s ; p = i sig t / s
+                const T c = sig * s.inv_ntot / s.s;
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (d < D) v[d][e] = rmul(c, mul_i(cmul(gg[d], wp)));
+                if (D == 3) v[3][e] = rmul(c, mul_i(t));
+                else v[2][e] = rmul(c, mul_i(t));
+            }
+        }
+    }
+
+    // inverse FFT from the registers and store
+    using QI = Seq<P, 1>;
+    constexpr int RL = QI::r(P::S - 1);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (f < F) {
+            __syncthreads();
+            fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
+            const int64_t pb = (int64_t)f * g.ncell + base;
+#pragma unroll
+            for (int b = 0; b < N / (RL * P::TPC); ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) w[pb + (int64_t)out_index<P, 1>(lane, b, r) * es] = v[f][b * RL + r];
+        }
+    }
+}
+
+// ---------------------------------------------------------- reductions --
+// One block per slot.  CBS: advance the iteration counter, compute the
+// relative update |dx| / |x_k| (skipped while x_k = 0, i.e. the first
+// iteration), raise done on tolerance, cap, non-finite values or three
+// consecutive updates larger than twice the iterate.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_cbs(const Slot<T>* slots, int nparts) {
+    __shared__ double red[16];
+    Ctl* c = slots[blockIdx.x].ctl;
+    if (c->done) return;
+    const double* p = slots[blockIdx.x].partials;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a += p[2 * i];
+        b += p[2 * i + 1];
+    }
+    block_sum2(a, b, red);
+    if (threadIdx.x == 0) {
+        const int it = c->iter + 1;
+        c->iter = it;
+        const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+        c->rel_update = rel;
+        c->xnorm2 = b;
+        int done = RUNNING;
+        if (!isfinite(a) || !isfinite(b)) {
+            done = DIVERGED;
+        } else {
+            c->grow = (it >= 3 && rel > 2.0) ? c->grow + 1 : 0;
+            if (c->grow >= 3) done = DIVERGED;
+            else if (b > 0.0 && rel <= c->tol) done = CONVERGED;
+            else if (it >= c->max_iter) done = CAPPED;
+        }
+        c->done = done;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_apply(const Slot<T>* slots, int nparts) {
+    __shared__ double red[16];
+    Ctl* c = slots[blockIdx.x].ctl;
+    const double* p = slots[blockIdx.x].partials;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        a += p[2 * i];
+        b += p[2 * i + 1];
+    }
+    block_sum2(a, b, red);
+    if (threadIdx.x == 0) {
+        c->res2 = a;
+        c->rhs2 = b;
+        c->scale = sqrt(a);
+        c->res_done += 1;
+    }
+}
+
+__global__ void k_ctl_reset(Ctl* c, int max_iter, double tol) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->done = RUNNING;
+        c->iter = 0;
+        c->max_iter = max_iter;
+        c->grow = 0;
+        c->tol = tol;
+        c->rel_update = 0.0;
+        c->xnorm2 = 0.0;
+    }
+}
+
+// ------------------------------------------------------- elementwise --
+template <typename T>
+__global__ void k_zero(cx<T>* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = {T(0), T(0)};
+}
+
+// y = C^{-1/2} s_hat for every field, written at both precisions (either
+// destination nullable).  kind PHYSICAL forms s_hat from the physical
+// sources (rhobar s_u, q s_p); EQUATION takes them as given.  su may be null.
+__global__ void k_rhs(Geom g, const cx<double>* sp, const cx<double>* su, const double* rhobar,
+                      const cx<double>* q, int physical, double il1s, double il2s, cx<double>* y64,
+                      cx<float>* y32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int F = g.ndim + 1;
+    if (i >= g.ncell * F) return;
+    const int f = (int)(i / g.ncell);
+    const int64_t cell = i % g.ncell;
+    cx<double> v;
+    if (f < g.ndim) {
+        v = su ? su[i] : cx<double>{0.0, 0.0};
+        if (physical) v = rmul(rhobar[i], v);
+        v = rmul(il1s, v);
+    } else {
+        v = sp[cell];
+        if (physical) v = cmul(q[cell], v);
+        v = rmul(il2s, v);
+    }
+    if (y64) y64[i] = v;
+    if (y32) y32[i] = {(float)v.re, (float)v.im};
+}
+
+// x = C^{1/2} (u, p) from physical fields (u nullable).
+__global__ void k_scale_in(Geom g, const cx<double>* p, const cx<double>* u, double sl1, double sl2,
+                           cx<double>* x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int F = g.ndim + 1;
+    if (i >= g.ncell * F) return;
+    const int f = (int)(i / g.ncell);
+    if (f < g.ndim) x[i] = u ? rmul(sl1, u[i]) : cx<double>{0.0, 0.0};
+    else x[i] = rmul(sl2, p[i % g.ncell]);
+}
+
+// (u, p) = C^{-1/2} x into complex128 outputs (u nullable); T = state precision.
+template <typename T>
+__global__ void k_unscale(Geom g, const cx<T>* x, double il1s, double il2s, cx<double>* p, cx<double>* u) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int F = g.ndim + 1;
+    if (i >= g.ncell * F) return;
+    const int f = (int)(i / g.ncell);
+    const cx<double> v = {(double)x[i].re, (double)x[i].im};
+    if (f < g.ndim) {
+        if (u) u[i] = rmul(il1s, v);
+    } else {
+        p[i % g.ncell] = rmul(il2s, v);
+    }
+}
+
+// physical residual C^{1/2} r from the scaled residual r
+__global__ void k_residual_out(Geom g, const cx<double>* r, double sl1, double sl2, cx<double>* rp,
+                               cx<double>* ru) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int F = g.ndim + 1;
+    if (i >= g.ncell * F) return;
+    const int f = (int)(i / g.ncell);
+    if (f < g.ndim) {
+        if (ru) ru[i] = rmul(sl1, r[i]);
+    } else if (rp) {
+        rp[i % g.ncell] = rmul(sl2, r[i]);
+    }
+}
+
+// refinement: inner right-hand side r / |r| in FP32 (|r| read on device)
+__global__ void k_convert(const cx<double>* r, cx<float>* y32, int64_t n, const Ctl* c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double inv = c->scale > 0.0 ? 1.0 / c->scale : 0.0;
+    y32[i] = {(float)(r[i].re * inv), (float)(r[i].im * inv)};
+}
+
+// refinement: x64 += |r| d32
+__global__ void k_accumulate(cx<double>* x, const cx<float>* d, int64_t n, const Ctl* c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double sc = c->scale;
+    x[i] = {x[i].re + sc * (double)d[i].re, x[i].im + sc * (double)d[i].im};
+}
+
+// Misfit gradient (adjoint-state) per cell; see cbs_gradient in cbs.h.
+__global__ void k_gradient(Geom g, const double* c, const double* rho, const double* alpha,
+                           const cx<double>* q, const double* gcen0, const double* gcen1,
+                           const double* gcen2, const double* gst0, const double* gst1,
+                           const double* gst2, double gmax, double omega, const cx<double>* sp,
+                           const cx<double>* su, const cx<double>* p, const cx<double>* u,
+                           const cx<double>* lp, const cx<double>* lu, double* gc, double* grho,
+                           double* galpha) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.ncell) return;
+    int ix[3];
+    cell_coords(g, i, ix);
+    const double* gcen[3] = {gcen0, gcen1, gcen2};
+    const double* gst[3] = {gst0, gst1, gst2};
+    double gsum = 0.0;
+    for (int d = 0; d < g.ndim; ++d) gsum += gcen[d][ix[d]];
+    const double gam = gmax * gsum;
+    const double cv = c[i], rv = rho[i], av = alpha[i];
+    const cx<double> iwg = {gam, omega};
+    // conj(lambda_p) (s_p - (gamma + i w) p): common factor of the pressure row
+    const cx<double> core = cmulc(sp[i] - cmul(iwg, p[i]), lp[i]);
+    const cx<double> dq_dc = {-2.0 / (cv * cv * cv * rv), 2.0 * av / (omega * cv * cv * rv)};
+    const cx<double> dq_dal = {0.0, -2.0 / (omega * rv * cv)};
+    const cx<double> qv = q[i];
+    const cx<double> dq_drho = {-qv.re / rv, -qv.im / rv};
+    if (gc) gc[i] = cmul(core, dq_dc).re;
+    if (galpha) galpha[i] = cmul(core, dq_dal).re;
+    if (grho) {
+        double gr = cmul(core, dq_drho).re;
+        if (u && lu) {
+            for (int e = 0; e < g.ndim; ++e) {
+                // rhobar_e at this cell and at the cell one step back along e
+                int jx[3] = {ix[0], ix[1], ix[2]};
+                jx[e] = (jx[e] - 1 + g.n[e]) % g.n[e];
+                int64_t j = 0;
+                for (int d = 0; d < g.ndim; ++d) j = j * g.n[d] + (d < g.ndim ? jx[d] : 0);
+                for (int which = 0; which < 2; ++which) {
+                    const int64_t cell = which ? j : i;
+                    const int* cc = which ? jx : ix;
+                    double gs = 0.0;
+                    for (int d = 0; d < g.ndim; ++d) gs += (d == e) ? gst[d][cc[d]] : gcen[d][cc[d]];
+                    const cx<double> iwe = {gmax * gs, omega};
+                    const int64_t k = (int64_t)e * g.ncell + cell;
+                    const cx<double> sv = su ? su[k] : cx<double>{0.0, 0.0};
+                    gr += 0.5 * cmulc(sv - cmul(iwe, u[k]), lu[k]).re;
+                }
+            }
+        }
+        grho[i] = gr;
+    }
+}
+
+// ------------------------------------------------------------ dispatch --
+// Supported axis lengths and their plans (radices, threads per column).
+#define CBS_PLANS(X)                  \
+    X(4, 4, 1, 1, 1)                  \
+    X(6, 6, 1, 1, 1)                  \
+    X(8, 8, 1, 1, 1)                  \
+    X(12, 12, 1, 1, 1)                \
+    X(16, 4, 4, 1, 4)                 \
+    X(24, 4, 6, 1, 2)                 \
+    X(32, 4, 8, 1, 4)                 \
+    X(48, 4, 12, 1, 4)                \
+    X(64, 8, 8, 1, 8)                 \
+    X(96, 4, 4, 6, 8)                 \
+    X(128, 8, 16, 1, 8)               \
+    X(192, 4, 4, 12, 16)              \
+    X(256, 16, 16, 1, 16)
+
+// Alternative plans with fewer elements per thread (for register-heavy
+// passes in FP64).
+#define CBS_PLANS_WIDE(X)             \
+    X(64, 4, 4, 4, 16)                \
+    X(128, 4, 4, 8, 16)               \
+    X(256, 4, 8, 8, 32)
+
+int plan_tpc(int n, bool wide) {
+#define TPC_CASE(N_, A, B, C, T_) \
+    if (n == N_) return T_;
+    if (wide) { CBS_PLANS_WIDE(TPC_CASE) }
+    CBS_PLANS(TPC_CASE)
+#undef TPC_CASE
+    return 0;
+}
+
+bool plan_has_wide(int n) { return n == 64 || n == 128 || n == 256; }
+
+// Launch one pass.  kind: 0 contiguous-first, 1 contiguous-last, 2 strided
+// forward, 3 strided inverse, 4 propagator.
+template <typename T, class P>
+static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis,
+                              int pcols, hipStream_t st) {
+    const int N = P::N;
+    const int ldp = pcols + 1;
+    size_t lds = (size_t)N * ldp * sizeof(cx<T>);
+    if (lds < 64 * sizeof(double)) lds = 64 * sizeof(double);
+    const dim3 block(pcols * P::TPC);
+    const int F = g.ndim + 1;
+    const int last = g.ndim - 1;
+    if (kind == 0 || kind == 1) {
+        const int64_t tiles = g.ncell / ((int64_t)N * pcols);
+        const dim3 grid((unsigned)tiles, F, nslots);
+        if (kind == 0) {
+            if (mode == CBS)
+                hipLaunchKernelGGL((k_contig<P, CBS, true, T>), grid, block, lds, st, slots, g, pcols, ldp);
+            else
+                hipLaunchKernelGGL((k_contig<P, APPLY, true, T>), grid, block, lds, st, slots, g, pcols, ldp);
+        } else {
+            if (mode == CBS)
+                hipLaunchKernelGGL((k_contig<P, CBS, false, T>), grid, block, lds, st, slots, g, pcols, ldp);
+            else
+                hipLaunchKernelGGL((k_contig<P, APPLY, false, T>), grid, block, lds, st, slots, g, pcols, ldp);
+        }
+    } else {
+        // strided along `axis`; columns run along the last axis in groups of pcols
+        int64_t es = 1;
+        for (int d = axis + 1; d < g.ndim; ++d) es *= g.n[d];
+        const int nlast_tiles = g.n[last] / pcols;
+        // the remaining ("other") axis: the one that is neither `axis` nor last
+        int other = -1;
+        for (int d = 0; d < g.ndim - 1; ++d)
+            if (d != axis) other = d;
+        int64_t ostride = 0;
+        int nother = 1;
+        if (other >= 0) {
+            ostride = 1;
+            for (int d = other + 1; d < g.ndim; ++d) ostride *= g.n[d];
+            nother = g.n[other];
+        }
+        const unsigned tiles = (unsigned)(nlast_tiles * nother);
+        if (kind == 4) {
+            const dim3 grid(tiles, 1, nslots);
+            if (mode == CBS)
+                hipLaunchKernelGGL((k_prop<P, CBS, T>), grid, block, lds, st, slots, g, pcols, ldp, es, ostride,
+                                   nlast_tiles);
+            else
+                hipLaunchKernelGGL((k_prop<P, APPLY, T>), grid, block, lds, st, slots, g, pcols, ldp, es, ostride,
+                                   nlast_tiles);
+        } else {
+            const dim3 grid(tiles, F, nslots);
+            const int skip = mode == CBS ? 1 : 0;
+            if (kind == 2)
+                hipLaunchKernelGGL((k_strided<P, -1, T>), grid, block, lds, st, slots, g, axis, pcols, ldp, es,
+                                   ostride, nlast_tiles, skip);
+            else
+                hipLaunchKernelGGL((k_strided<P, 1, T>), grid, block, lds, st, slots, g, axis, pcols, ldp, es,
+                                   ostride, nlast_tiles, skip);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
+                       int pcols, bool wide, hipStream_t st) {
+#define LAUNCH_CASE(N_, A, B, C, T_) \
+    if (n == N_) return launch_plan<T, Plan<N_, A, B, C, T_>>(kind, mode, slots, nslots, g, axis, pcols, st);
+    if (wide) { CBS_PLANS_WIDE(LAUNCH_CASE) }
+    CBS_PLANS(LAUNCH_CASE)
+#undef LAUNCH_CASE
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_pass<float>(int, int, const Slot<float>*, int, const Geom&, int, int, int, bool,
+                                       hipStream_t);
+template hipError_t launch_pass<double>(int, int, const Slot<double>*, int, const Geom&, int, int, int, bool,
+                                        hipStream_t);
+
+template <typename T>
+hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st) {
+    if (cbs_mode)
+        hipLaunchKernelGGL((k_reduce_cbs<T>), dim3(nslots), dim3(256), 0, st, slots, nparts);
+    else
+        hipLaunchKernelGGL((k_reduce_apply<T>), dim3(nslots), dim3(256), 0, st, slots, nparts);
+    return hipGetLastError();
+}
+template hipError_t launch_reduce<float>(bool, const Slot<float>*, int, int, hipStream_t);
+template hipError_t launch_reduce<double>(bool, const Slot<double>*, int, int, hipStream_t);
+
+hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, c, max_iter, tol);
+    return hipGetLastError();
+}
+
+static inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+template <typename T>
+hipError_t launch_zero(cx<T>* p, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_zero<T>), grid1(n), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+template hipError_t launch_zero<float>(cx<float>*, int64_t, hipStream_t);
+template hipError_t launch_zero<double>(cx<double>*, int64_t, hipStream_t);
+
+hipError_t launch_rhs(const Geom& g, const cx<double>* sp, const cx<double>* su, const double* rhobar,
+                      const cx<double>* q, int physical, double il1s, double il2s, cx<double>* y64,
+                      cx<float>* y32, hipStream_t st) {
+    hipLaunchKernelGGL(k_rhs, grid1(g.ncell * (g.ndim + 1)), dim3(256), 0, st, g, sp, su, rhobar, q, physical,
+                       il1s, il2s, y64, y32);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_in(const Geom& g, const cx<double>* p, const cx<double>* u, double sl1, double sl2,
+                           cx<double>* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_in, grid1(g.ncell * (g.ndim + 1)), dim3(256), 0, st, g, p, u, sl1, sl2, x);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_unscale(const Geom& g, const cx<T>* x, double il1s, double il2s, cx<double>* p,
+                          cx<double>* u, hipStream_t st) {
+    hipLaunchKernelGGL((k_unscale<T>), grid1(g.ncell * (g.ndim + 1)), dim3(256), 0, st, g, x, il1s, il2s, p, u);
+    return hipGetLastError();
+}
+template hipError_t launch_unscale<float>(const Geom&, const cx<float>*, double, double, cx<double>*,
+                                          cx<double>*, hipStream_t);
+template hipError_t launch_unscale<double>(const Geom&, const cx<double>*, double, double, cx<double>*,
+                                           cx<double>*, hipStream_t);
+
+hipError_t launch_residual_out(const Geom& g, const cx<double>* r, double sl1, double sl2, cx<double>* rp,
+                               cx<double>* ru, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual_out, grid1(g.ncell * (g.ndim + 1)), dim3(256), 0, st, g, r, sl1, sl2, rp, ru);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const cx<double>* r, cx<float>* y32, int64_t n, const Ctl* c, hipStream_t st) {
+    hipLaunchKernelGGL(k_convert, grid1(n), dim3(256), 0, st, r, y32, n, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(cx<double>* x, const cx<float>* d, int64_t n, const Ctl* c, hipStream_t st) {
+    hipLaunchKernelGGL(k_accumulate, grid1(n), dim3(256), 0, st, x, d, n, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradient(const Geom& g, const double* c, const double* rho, const double* alpha,
+                           const cx<double>* q, const double* const* gcen, const double* const* gst, double gmax,
+                           double omega, const cx<double>* sp, const cx<double>* su, const cx<double>* p,
+                           const cx<double>* u, const cx<double>* lp, const cx<double>* lu, double* gc,
+                           double* grho, double* galpha, hipStream_t st) {
+    hipLaunchKernelGGL(k_gradient, grid1(g.ncell), dim3(256), 0, st, g, c, rho, alpha, q, gcen[0], gcen[1],
+                       gcen[2], gst[0], gst[1], gst[2], gmax, omega, sp, su, p, u, lp, lu, gc, grho, galpha);
+    return hipGetLastError();
+}
+
+}  // namespace cbs

@@ -1,0 +1,233 @@
+"""Python binding of the gfx950 solver: argument marshalling over the C ABI.
+
+Every step of the solve runs in the HIP library; this module only converts
+arrays to pointers and allocates caller-owned device memory (workspaces,
+outputs) through torch's allocator.  Host inputs may be numpy arrays
+(pointer kind HOST); device inputs are torch CUDA tensors (kind DEVICE).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+PREC = {"fp64": L.CBS_FP64, "fp32_refined": L.CBS_FP32_REFINED}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _is_tensor(a) -> bool:
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(a, torch.Tensor)
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if _is_tensor(a):
+        return C.c_void_p(a.data_ptr())
+    return C.c_void_p(a.ctypes.data)
+
+
+def _host_c128(a, count):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.size != count:
+        raise ValueError(f"expected {count} complex values, got {a.size}")
+    return a
+
+
+def _dev_c128(a, count):
+    if a is None:
+        return None
+    torch = _torch()
+    if a.dtype != torch.complex128 or not a.is_contiguous() or not a.is_cuda:
+        raise ValueError("device arrays must be contiguous complex128 CUDA tensors")
+    if a.numel() != count:
+        raise ValueError(f"expected {count} complex values, got {a.numel()}")
+    return a
+
+
+class Medium:
+    """A medium (c, rho, alpha on the grid) planned for the solver."""
+
+    def __init__(self, shape: Sequence[int], dx: float, omega: float, c, rho, alpha,
+                 pml: int = 16, gamma_max: float = 0.0, beta: float = 0.95, nu: float = 0.9,
+                 shift_rule: int = 0, stream=None):
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.ncell = int(np.prod(self.shape))
+        self.F = self.ndim + 1
+        self.dx, self.omega = float(dx), float(omega)
+        g = L.Grid()
+        g.ndim = self.ndim
+        for d in range(3):
+            g.n[d] = self.shape[d] if d < self.ndim else 1
+        g.dx, g.omega, g.pml_cells, g.pml_gamma_max = self.dx, self.omega, int(pml), float(gamma_max)
+        g.beta, g.nu, g.shift_rule = float(beta), float(nu), int(shift_rule)
+        self.grid = g
+        if _is_tensor(c):
+            arrs = [t.contiguous().to(_torch().float64) for t in (c, rho, alpha)]
+            kind = L.CBS_PTR_DEVICE
+            sp = _stream_ptr(stream)
+        else:
+            arrs = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (c, rho, alpha)]
+            kind = L.CBS_PTR_HOST
+            sp = _stream_ptr(stream) if _torch().cuda.is_available() else None
+        for a in arrs:
+            if (a.numel() if _is_tensor(a) else a.size) != self.ncell:
+                raise ValueError("medium arrays must have prod(shape) cells")
+        h = C.c_void_p()
+        L.check(L.lib().cbs_create_medium(C.byref(g), *[_ptr(a) for a in arrs], kind, sp,
+                                          C.byref(h)), "cbs_create_medium")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            L.lib().cbs_destroy_medium(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def scalars(self) -> dict:
+        o = (C.c_double * 8)()
+        L.check(L.lib().cbs_medium_scalars(self._h, o), "cbs_medium_scalars")
+        return dict(a1=complex(o[0], o[1]), a2=complex(o[2], o[3]), lam1=o[4], lam2=o[5],
+                    beta=o[6], nu=o[7])
+
+    def set_scalars(self, a1, a2, lam1, lam2):
+        v = (C.c_double * 6)(a1.real, a1.imag, a2.real, a2.imag, lam1, lam2)
+        L.check(L.lib().cbs_set_scalars(self._h, v), "cbs_set_scalars")
+
+    def workspace_bytes(self, prec="fp64", batch=1) -> int:
+        b = C.c_size_t()
+        L.check(L.lib().cbs_workspace_bytes(self._h, PREC[prec], int(batch), C.byref(b)),
+                "cbs_workspace_bytes")
+        return b.value
+
+    def workspace(self, prec="fp64"):
+        torch = _torch()
+        return torch.empty(self.workspace_bytes(prec), dtype=torch.uint8, device="cuda")
+
+
+def _opts(tol, max_iter, prec, check_every, inner_tol, rhs_kind, ptr_kind, stop_rule, max_outer):
+    o = L.SolveOpts()
+    o.tol, o.max_iter, o.prec = float(tol), int(max_iter), PREC[prec]
+    o.check_every, o.inner_tol = int(check_every), float(inner_tol)
+    o.rhs_kind, o.ptr_kind, o.stop_rule, o.max_outer = int(rhs_kind), int(ptr_kind), int(stop_rule), int(max_outer)
+    return o
+
+
+def solve(m: Medium, s_p, s_u=None, *, tol=1e-8, max_iter=100000, prec="fp64", check_every=32,
+          inner_tol=0.0, equation_rhs=False, stop_rule=L.CBS_STOP_UPDATE, max_outer=0,
+          adjoint=False, want_u=True, workspace=None, stream=None, raise_on_cap=False):
+    """Solve A xi = s_hat (or A^H xi = s_hat).  Returns (p, u, info).
+
+    numpy inputs give numpy outputs (host pointers); CUDA tensors give CUDA
+    tensors (device pointers, no host copies)."""
+    device = _is_tensor(s_p)
+    N = m.ncell
+    if device:
+        torch = _torch()
+        sp = _dev_c128(s_p.reshape(-1), N)
+        su = _dev_c128(s_u.reshape(-1), m.ndim * N) if s_u is not None else None
+        p = torch.empty(N, dtype=torch.complex128, device=sp.device)
+        u = torch.empty(m.ndim * N, dtype=torch.complex128, device=sp.device) if want_u else None
+        kind = L.CBS_PTR_DEVICE
+    else:
+        sp = _host_c128(s_p, N)
+        su = _host_c128(s_u, m.ndim * N)
+        p = np.empty(N, np.complex128)
+        u = np.empty(m.ndim * N, np.complex128) if want_u else None
+        kind = L.CBS_PTR_HOST
+    ws = workspace if workspace is not None else m.workspace(prec)
+    o = _opts(tol, max_iter, prec, check_every, inner_tol,
+              L.CBS_RHS_EQUATION if equation_rhs else L.CBS_RHS_PHYSICAL, kind, stop_rule, max_outer)
+    info = L.SolveInfo()
+    fn = L.lib().cbs_solve_adjoint if adjoint else L.lib().cbs_solve
+    st = fn(m.handle, _ptr(sp), _ptr(su), C.byref(o), _ptr(p), _ptr(u), C.c_void_p(ws.data_ptr()),
+            ws.numel(), C.byref(info), _stream_ptr(stream))
+    allow = (L.CBS_OK,) if raise_on_cap else (L.CBS_OK, L.CBS_NOT_CONVERGED)
+    L.check(st, "cbs_solve_adjoint" if adjoint else "cbs_solve", allow)
+    d = info.as_dict()
+    d["converged"] = st == L.CBS_OK
+    p = p.reshape(m.shape)
+    if u is not None:
+        u = u.reshape((m.ndim,) + m.shape)
+    return p, u, d
+
+
+def residual(m: Medium, s_p, s_u, p, u=None, *, adjoint=False, equation_rhs=False,
+             want_fields=False, workspace=None, stream=None):
+    """Scaled FP64 residual |y - (L+V) x| / |y|; optionally the physical
+    residual fields (r_p, r_u)."""
+    device = _is_tensor(p)
+    N = m.ncell
+    if device:
+        torch = _torch()
+        args = [_dev_c128(s_p.reshape(-1), N),
+                _dev_c128(s_u.reshape(-1), m.ndim * N) if s_u is not None else None,
+                _dev_c128(p.reshape(-1), N),
+                _dev_c128(u.reshape(-1), m.ndim * N) if u is not None else None]
+        rp = torch.empty(N, dtype=torch.complex128, device=p.device) if want_fields else None
+        ru = torch.empty(m.ndim * N, dtype=torch.complex128, device=p.device) if want_fields else None
+        kind = L.CBS_PTR_DEVICE
+    else:
+        args = [_host_c128(s_p, N), _host_c128(s_u, m.ndim * N), _host_c128(p, N),
+                _host_c128(u, m.ndim * N)]
+        rp = np.empty(N, np.complex128) if want_fields else None
+        ru = np.empty(m.ndim * N, np.complex128) if want_fields else None
+        kind = L.CBS_PTR_HOST
+    ws = workspace if workspace is not None else m.workspace("fp64")
+    rel = C.c_double()
+    L.check(L.lib().cbs_residual(m.handle, *[_ptr(a) for a in args], int(adjoint),
+                                 L.CBS_RHS_EQUATION if equation_rhs else L.CBS_RHS_PHYSICAL, kind,
+                                 C.byref(rel), _ptr(rp), _ptr(ru), C.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream_ptr(stream)), "cbs_residual")
+    if want_fields:
+        return rel.value, rp.reshape(m.shape), ru.reshape((m.ndim,) + m.shape)
+    return rel.value
+
+
+def gradient(m: Medium, s_p, s_u, p, u, lp, lu, stream=None):
+    """Adjoint-state misfit gradient (dJ/dc, dJ/drho, dJ/dalpha)."""
+    device = _is_tensor(p)
+    N = m.ncell
+    if device:
+        torch = _torch()
+        args = [_dev_c128(s_p.reshape(-1), N),
+                _dev_c128(s_u.reshape(-1), m.ndim * N) if s_u is not None else None,
+                _dev_c128(p.reshape(-1), N),
+                _dev_c128(u.reshape(-1), m.ndim * N) if u is not None else None,
+                _dev_c128(lp.reshape(-1), N),
+                _dev_c128(lu.reshape(-1), m.ndim * N) if lu is not None else None]
+        outs = [torch.empty(N, dtype=torch.float64, device=p.device) for _ in range(3)]
+        kind = L.CBS_PTR_DEVICE
+    else:
+        args = [_host_c128(s_p, N), _host_c128(s_u, m.ndim * N), _host_c128(p, N),
+                _host_c128(u, m.ndim * N), _host_c128(lp, N), _host_c128(lu, m.ndim * N)]
+        outs = [np.empty(N) for _ in range(3)]
+        kind = L.CBS_PTR_HOST
+    L.check(L.lib().cbs_gradient(m.handle, *[_ptr(a) for a in args], kind,
+                                 *[_ptr(o) for o in outs], _stream_ptr(stream) if device else None),
+            "cbs_gradient")
+    return tuple(o.reshape(m.shape) for o in outs)

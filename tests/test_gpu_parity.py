@@ -1,0 +1,135 @@
+"""GPU parity against the FP64 oracle, through the C ABI.
+
+* planner: shifts a1, a2 and scales lam1, lam2 (Algorithm 1 preprocessing,
+  eqs. LV and C) equal the oracle's to rounding;
+* FP64 iterate-for-iterate: after K iterations of eq. BornAlt the GPU state
+  equals the oracle's K-th iterate to 1e-10 relative L2 (forward and adjoint);
+* FP64 converged: both solved to 1e-12 agree to 1e-10;
+* refined FP32: within 1e-5 of the oracle's FP64 solution;
+* residual and gradient entry points against the oracle's.
+Shapes span several column tiles, radix-2/3/4/6/8/12/16 stages and 2-D / 3-D.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_16087_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+OMEGA = 2 * np.pi * 1e6
+DX = 1500.0 / 1e6 / 6
+
+
+@pytest.fixture(scope="module")
+def cbs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_16087_amd import solver
+    return solver
+
+
+def _pair(orc, cbs, shape, seed=3, pml=4, **kw):
+    c, rho, alpha = W.small_random(shape, seed)
+    om = orc.OracleMedium(shape, DX, OMEGA, c, rho, alpha, pml=pml, **kw)
+    gm = cbs.Medium(shape, DX, OMEGA, c, rho, alpha, pml=pml, **kw)
+    return om, gm
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+SHAPES = [(24, 32), (96, 16), (12, 192), (16, 24, 32), (8, 96, 12), (6, 16, 48), (32, 8, 64)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("rule", [0, 1])
+def test_planner_scalars_match_oracle(orc, cbs, shape, rule):
+    om, gm = _pair(orc, cbs, shape, shift_rule=rule, pml=2)
+    so, sg = om.scalars(), gm.scalars()
+    for k in ("a1", "a2"):
+        assert abs(so[k] - sg[k]) <= 1e-12 * abs(so[k]), (k, so[k], sg[k])
+    for k in ("lam1", "lam2"):
+        assert abs(so[k] - sg[k]) <= 1e-12 * so[k], (k, so[k], sg[k])
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(128, 128), (64, 64, 64)])
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("iters", [1, 7, 60])
+def test_fp64_iterates_match_oracle(orc, cbs, shape, adjoint, iters):
+    om, gm = _pair(orc, cbs, shape, pml=2)
+    rng = np.random.default_rng(17)
+    F = len(shape) + 1
+    s = np.zeros((F,) + shape, complex)
+    flat = s.reshape(F, -1)
+    idx = rng.choice(flat.shape[1], 5, replace=False)
+    flat[-1, idx] = rng.standard_normal(5) + 1j * rng.standard_normal(5)
+    flat[0, idx[:2]] = 0.3 - 0.1j          # a velocity source too
+    xi, info = om.solve(om.source_hat(s), tol=0.0, max_iter=iters, adjoint=adjoint)
+    p, u, ginfo = cbs.solve(gm, s[-1], s[:-1], tol=0.0, max_iter=iters, adjoint=adjoint)
+    assert ginfo["iterations"] == iters and not ginfo["converged"]
+    assert _rel(p, xi[-1]) <= 1e-10
+    assert _rel(u, xi[:-1]) <= 1e-10
+
+
+def test_fp64_converged_disc2d(orc, cbs):
+    """The 2-D disc workload (128 x 128, c 1800 / rho 1500 inclusion) solved to
+    a relative update of 1e-12 on both sides."""
+    pr = W.disc2d()
+    om = orc.OracleMedium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
+    gm = cbs.Medium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
+    sp = pr.dense_source()
+    xi, info = om.solve(om.source_hat(om.pressure_source(sp)), tol=1e-12, max_iter=200000)
+    p, u, ginfo = cbs.solve(gm, sp, tol=1e-12, max_iter=200000, check_every=64)
+    assert info["converged"] and ginfo["converged"]
+    assert ginfo["iterations"] == info["iterations"]
+    assert _rel(p, xi[-1]) <= 1e-10
+    assert _rel(u, xi[:-1]) <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [(64, 96), (24, 32, 48)])
+def test_fp32_refined_matches_oracle(orc, cbs, shape):
+    om, gm = _pair(orc, cbs, shape, pml=4)
+    sp = np.zeros(shape, complex)
+    sp[tuple(n // 2 for n in shape)] = 1.0
+    xi, info = om.solve(om.source_hat(om.pressure_source(sp)), tol=1e-12, max_iter=200000)
+    p, u, ginfo = cbs.solve(gm, sp, tol=1e-7, prec="fp32_refined", inner_tol=1e-4)
+    assert ginfo["converged"] and ginfo["outer"] >= 1
+    assert ginfo["rel_residual"] <= 1e-7
+    assert _rel(p, xi[-1]) <= 1e-5
+    assert _rel(u, xi[:-1]) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(32, 48), (12, 16, 24)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_residual_matches_oracle(orc, cbs, shape, adjoint):
+    om, gm = _pair(orc, cbs, shape, pml=2)
+    rng = np.random.default_rng(4)
+    F = len(shape) + 1
+    xi = rng.standard_normal((F,) + shape) + 1j * rng.standard_normal((F,) + shape)
+    s = rng.standard_normal((F,) + shape) + 1j * rng.standard_normal((F,) + shape)
+    shat = om.source_hat(s)
+    rel_o = om.rel_residual(shat, xi, adjoint)
+    rel_g, rp, ru = cbs.residual(gm, s[-1], s[:-1], xi[-1], xi[:-1], adjoint=adjoint,
+                                 want_fields=True)
+    assert abs(rel_g - rel_o) <= 1e-12 * rel_o
+    r = shat - om.apply_A(xi, adjoint)
+    assert _rel(rp, r[-1]) <= 1e-12
+    assert _rel(ru, r[:-1]) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(24, 32), (8, 12, 16)])
+def test_gradient_kernel_matches_oracle(orc, cbs, shape):
+    om, gm = _pair(orc, cbs, shape, pml=2)
+    rng = np.random.default_rng(6)
+    F = len(shape) + 1
+
+    def rc():
+        return rng.standard_normal((F,) + shape) + 1j * rng.standard_normal((F,) + shape)
+
+    s, xi, lam = rc(), rc(), rc()
+    go = om.gradient(s, xi, lam)
+    gg = cbs.gradient(gm, s[-1], s[:-1], xi[-1], xi[:-1], lam[-1], lam[:-1])
+    for a, b in zip(gg, go):
+        assert _rel(a, b) <= 1e-12
