@@ -1,0 +1,209 @@
+"""Benchmark: Gcell-iterations/s and time-to-1e-5 of the iterative Born solver
+on one MI355X, refined FP32 against plain FP64, on the 256^3 skull-like shell
+workload (500 kHz, dx = 0.5 mm, bone shell with porosity, focused-bowl source).
+
+A step is one complete solve to a scaled FP64 residual of 1e-5 with the medium
+resident on the device: right-hand side, every CBS iteration (five FFT passes
+with the fused propagator and update), FP64 true residuals and refinement
+accumulations, and the unscaled output.  Inputs are synthetic (seeded), built
+before the timed region.
+
+Prints one JSON line.  Fields beyond the driver contract:
+  time_to_tol_ms   -- wall time per solve, refined FP32 and plain FP64
+  iterations       -- CBS iterations per solve, each path
+  passes           -- per-pass average duration (HIP events) and achieved GB/s
+  roofline         -- dominant kernel against the 8 TB/s HBM peak
+  cpu_baseline     -- the FP64 oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell per launch of each pass (F = 4 fields, FP32):
+#  - last-axis forward with prologue (first iteration of a run only): reads
+#    x, y (4 complex64 each), rhobar (3 f32) and q (complex64), writes w:
+#    32 + 32 + 20 + 32 = 116;
+#  - strided forward / inverse, axis-0 propagator: read and write w: 64;
+#  - last-axis inverse fused with the update and the next prologue: reads w,
+#    x, y and the medium, writes x and w: 32 * 3 + 20 + 32 * 2 = 180.
+PASS_NAMES = ["fwd_axis2_prologue", "fwd_axis1", "axis0_propagator", "inv_axis1",
+              "inv_axis2_update_fwd_axis2"]
+PASS_BYTES_F32 = [116, 64, 64, 64, 180]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def oracle_baseline(prob, iters: int):
+    """Time the FP64 oracle (plain C, OpenMP) for `iters` CBS iterations."""
+    from oracle import core as orc
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    m = orc.OracleMedium(prob.shape, prob.dx, prob.omega, prob.c, prob.rho, prob.alpha,
+                         pml=prob.pml_cells)
+    shat = m.source_hat(m.pressure_source(prob.dense_source()))
+    t0 = time.perf_counter()
+    m.solve(shat, tol=0.0, max_iter=iters)
+    dt = time.perf_counter() - t0
+    return dict(value=prob.ncell * iters / dt / 1e9, unit="Gcell-iter/s", cores=threads,
+                kind="oracle",
+                sample=f"{iters} FP64 CBS iterations of the oracle on the same "
+                       f"{'x'.join(map(str, prob.shape))} workload ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--check-every", type=int, default=50)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--max-iter", type=int, default=200000,
+                    help="cap on inner iterations per solve (short profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_16087_amd import _lib, solver, workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"building workload shell3d n={args.n}")
+    prob = W.shell3d(args.n)
+    log(f"cells={prob.ncell} sources={prob.src_idx.size}")
+    t0 = time.perf_counter()
+    m = solver.Medium(prob.shape, prob.dx, prob.omega, prob.c, prob.rho, prob.alpha,
+                      pml=prob.pml_cells)
+    setup_s = time.perf_counter() - t0
+    sp = torch.from_numpy(prob.dense_source().ravel()).to(dev)
+    ws32 = m.workspace("fp32_refined")
+    common = dict(tol=args.tol, prec="fp32_refined", check_every=args.check_every,
+                  inner_tol=args.inner_tol, workspace=ws32, want_u=True, max_iter=args.max_iter)
+
+    for i in range(args.warmup):
+        _, _, info = solver.solve(m, sp, **common)
+        log(f"warmup {i}: {info['iterations']} iterations, {info['outer']} outer, "
+            f"residual {info['rel_residual']:.2e}, {info['seconds']:.2f} s")
+
+    L = _lib.lib()
+    L.cbs_pass_timing(m.handle, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    infos = []
+    for i in range(args.steps):
+        p, u, info = solver.solve(m, sp, **common)
+        iters += info["iterations"]
+        infos.append(info)
+        log(f"step {i}: {info['iterations']} it, {info['outer']} outer, "
+            f"res {info['rel_residual']:.2e}, {info['seconds']:.2f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.cbs_pass_timing(m.handle, 0)
+    import ctypes as C
+    ms = (C.c_double * 18)()
+    cnt = (C.c_int64 * 18)()
+    L.cbs_pass_timing_read(m.handle, ms, cnt)
+    passes = {}
+    best = None
+    for k, name in enumerate(PASS_NAMES):
+        if cnt[k] == 0:
+            continue
+        avg = ms[k] / cnt[k]
+        gbs = PASS_BYTES_F32[k] * prob.ncell / (avg * 1e-3) / 1e9
+        passes[name] = dict(avg_ms=round(avg, 5), launches=int(cnt[k]), achieved_gbs=round(gbs, 1),
+                            bytes_per_cell=PASS_BYTES_F32[k])
+        if best is None or ms[k] > ms[best]:
+            best = k
+    total_pass_ms = sum(ms[k] for k in range(6))
+    fp64_res = {k: round(ms[12 + k] / cnt[12 + k], 5) for k in range(6) if cnt[12 + k]}
+
+    plans = {}
+    for prec_name, prec in (("fp32", _lib.CBS_FP32_REFINED), ("fp64", _lib.CBS_FP64)):
+        cfg = (C.c_int32 * 20)()
+        L.cbs_pass_config(m.handle, prec, cfg)
+        plans[prec_name] = [dict(kind=cfg[4 * i], n=cfg[4 * i + 1], cols=cfg[4 * i + 2], wide=cfg[4 * i + 3])
+                            for i in range(5) if cfg[4 * i] >= 0]
+    value = prob.ncell * iters / dt / 1e9
+    out = {
+        "metric": "Gcell-iter/s + time-to-1e-5 at 256^3, FP32-refined vs FP64 plain; p50/p99 ms",
+        "value": round(value, 4),
+        "unit": "Gcell-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"shell3d_{args.n}", "grid": list(prob.shape),
+                   "f_hz": 5e5, "dx_m": prob.dx, "tol": args.tol,
+                   "precision": "fp32 inner, fp64 residual/refinement",
+                   "sources": int(prob.src_idx.size), "pml_cells": prob.pml_cells},
+        "time_to_tol_ms": {"fp32_refined": round(dt / args.steps * 1e3, 2)},
+        "iterations": {"fp32_refined": infos[-1]["iterations"],
+                       "fp32_refined_outer": infos[-1]["outer"],
+                       "fp64_residual_evals": infos[-1]["residual_evals"]},
+        "final_residual": {"fp32_refined": infos[-1]["rel_residual"]},
+        "medium_setup_s": round(setup_s, 3),
+        "passes": passes,
+        "fp64_residual_pass_ms": fp64_res,
+        "pass_time_fraction": round(total_pass_ms / (dt * 1e3), 4),
+        "plans": plans,
+    }
+    if best is not None:
+        k = best
+        avg = ms[k] / cnt[k]
+        ach = PASS_BYTES_F32[k] * prob.ncell / (avg * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                           "kernel": PASS_NAMES[k],
+                           "bytes_per_launch": PASS_BYTES_F32[k] * prob.ncell,
+                           "avg_launch_ms": round(avg, 5)}
+
+    if not args.no_fp64:
+        ws64 = m.workspace("fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, i64 = solver.solve(m, sp, tol=args.tol, prec="fp64", check_every=args.check_every,
+                                 stop_rule=_lib.CBS_STOP_RESIDUAL, workspace=ws64, max_iter=200000)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        log(f"fp64: {i64['iterations']} it, res {i64['rel_residual']:.2e}, {t64:.2f} s")
+        out["time_to_tol_ms"]["fp64_plain"] = round(t64 * 1e3, 2)
+        out["iterations"]["fp64_plain"] = i64["iterations"]
+        out["final_residual"]["fp64_plain"] = i64["rel_residual"]
+        out["gcell_iter_s_fp64"] = round(prob.ncell * i64["iterations"] / t64 / 1e9, 4)
+        out["speedup_refined_vs_fp64"] = round(t64 / (dt / args.steps), 3)
+        del ws64
+
+    if not args.no_cpu:
+        del ws32
+        torch.cuda.empty_cache()
+        log("oracle baseline")
+        out["cpu_baseline"] = oracle_baseline(prob, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,26 @@ cbs_status cbs_gradient(cbs_medium m, const void *s_p, const void *s_u, const vo
                         const void *u, const void *lp, const void *lu, int32_t ptr_kind,
                         double *g_c, double *g_rho, double *g_alpha, void *hip_stream);
 
+/* Per-pass GPU time accounting for measurement: with enable = 1 (which also
+ * clears the totals) every pass launch of this medium's solves is bracketed
+ * by HIP events on the solve's stream and folded into running totals at each
+ * host synchronisation; enable = 0 stops recording. */
+cbs_status cbs_pass_timing(cbs_medium m, int32_t enable);
+
+/* Pass plans in use for precision prec (after the first solve tunes them):
+ * out[4 i + 0..3] = kind, axis length, columns per work-group, wide-plan flag
+ * of pass i (kind -1 = unused).  The first solve of each (shape, precision)
+ * in a process times the candidate plans on its workspace and keeps the
+ * fastest (set CBS_AUTOTUNE=0 in the environment to keep the defaults). */
+cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
+
+/* Totals so far: ms[g * 6 + k] and launches[g * 6 + k] for group g (0 FP32
+ * CBS iteration, 1 FP64 CBS iteration, 2 FP64 residual) and slot k (0..4 the
+ * passes in launch order -- contiguous forward, strided forward, axis-0
+ * propagator, strided inverse, contiguous inverse; 2-D grids use slots 0, 1,
+ * 2 -- and 5 the reduction). */
+cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18]);
+
 /* ---------------- batched slots (continuous-batching serving) -------------
  * A batch runs same-shape solves side by side: one kernel launch per pass
  * covers every active slot, iterations are captured in a HIP graph per

@@ -7,7 +7,10 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "cbs.h"
@@ -109,7 +112,10 @@ PassSet make_passes(const Geom& g, bool fp64) {
         p.wide = false;
         const int tpc = plan_tpc(p.n, false);
         const int64_t pencils = g.ncell / g.n[last];
-        p.pcols = pow2_floor_div(pencils, std::min(fp64 ? 16 : 32, 256 / tpc));
+        // whole pencils per work-group: at most 256 threads and ~40 KiB of LDS
+        const size_t pencil_lds = (size_t)(p.n + p.n / 16) * (fp64 ? 16 : 8);
+        const int lds_cap = (int)std::max<size_t>(1, (40 * 1024) / pencil_lds);
+        p.pcols = pow2_floor_div(pencils, std::min(256 / tpc, lds_cap));
         return p;
     };
     int k = 0;
@@ -239,13 +245,27 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 }  // namespace
 
 // ---------------------------------------------------------------- medium --
+// Per-pass GPU time accounting: HIP event pairs around every pass launch,
+// harvested whenever the driver synchronises.  Groups: 0 FP32 CBS, 1 FP64
+// CBS, 2 FP64 residual; slots 0..4 = passes in launch order, 5 = reduction.
+struct PassTiming {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> tag;
+    size_t used = 0;
+    double ms[3][6] = {};
+    int64_t cnt[3][6] = {};
+};
+
 struct cbs_medium_s {
+    PassTiming timing;
     Geom g;
     cbs_grid grid;
     double gmax, beta, nu;
     cd a1, a2;
     double lam1, lam2;
     PassSet ps64, ps32;
+    bool tuned64 = false, tuned32 = false;
     void* dev = nullptr;
     // device pointers into dev
     double *rhobar64, *c64, *rho64, *alpha64;
@@ -298,7 +318,7 @@ cx<T> tocx(cd v) {
 
 template <typename T>
 Slot<T> make_slot(const cbs_medium_s* m, cx<T>* x, cx<T>* w, const cx<T>* y, Ctl* ctl, double* partials,
-                  int adjoint) {
+                  int adjoint, double* chunks) {
     Slot<T> s{};
     s.x = x;
     s.w = w;
@@ -324,31 +344,199 @@ Slot<T> make_slot(const cbs_medium_s* m, cx<T>* x, cx<T>* w, const cx<T>* y, Ctl
     s.adjoint = adjoint;
     s.ctl = ctl;
     s.partials = partials;
+    s.chunks = chunks;
     return s;
 }
 
+hipError_t timing_begin(PassTiming& t, int tag, hipStream_t st) {
+    if (t.used + 2 > t.ev.size()) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            t.ev.push_back(e);
+            t.tag.push_back(0);
+        }
+    }
+    t.tag[t.used] = tag;
+    return hipEventRecord(t.ev[t.used], st);
+}
+
+hipError_t timing_end(PassTiming& t, hipStream_t st) {
+    hipError_t r = hipEventRecord(t.ev[t.used + 1], st);
+    t.used += 2;
+    return r;
+}
+
+// Fold recorded event pairs into the per-pass totals (stream already synced).
+// Launches that found their slot finished return at once; they are left out
+// (shorter than a quarter of the longest launch of the same pass in the batch).
+void timing_harvest(PassTiming& t) {
+    std::vector<float> dur(t.used / 2, -1.f);
+    float mx[24] = {};
+    for (size_t i = 0; i + 1 < t.used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]) == hipSuccess) {
+            dur[i / 2] = ms;
+            mx[t.tag[i]] = std::max(mx[t.tag[i]], ms);
+        }
+    }
+    for (size_t i = 0; i + 1 < t.used; i += 2) {
+        const float ms = dur[i / 2];
+        if (ms < 0.f || ms < 0.25f * mx[t.tag[i]]) continue;
+        const int g = t.tag[i] / 8, k = t.tag[i] % 8;
+        t.ms[g][k] += ms;
+        t.cnt[g][k] += 1;
+    }
+    t.used = 0;
+}
+
 // One CBS iteration (MODE_CBS) or one residual evaluation (MODE_APPLY) for
-// nslots same-shape slots.
+// nslots same-shape slots.  A CBS iteration ends with the fused pass that
+// updates x and already transforms the next iteration's B x + y along the
+// last axis, so only the first iteration of a run (start) launches the
+// stand-alone prologue pass.
+// Passes of one iteration for a set of same-shape slots.  In CBS mode the
+// stand-alone prologue pass runs only over `starts` (slots whose CBS run
+// begins with this iteration); the other passes run over `all`.
 template <typename T>
-hipError_t run_passes(const cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T>* dslots, int nslots,
-                      hipStream_t st) {
+hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int mode, const Slot<T>* all,
+                          int nall, const Slot<T>* starts, int nstart, hipStream_t st) {
+    const bool timed = tp && tp->on;
+    const int group = mode == MODE_APPLY ? 2 : (sizeof(T) == 8 ? 1 : 0);
     for (int i = 0; i < ps.count; ++i) {
         const Pass& p = ps.p[i];
-        hipError_t e = launch_pass<T>(p.kind, mode, dslots, nslots, m->g, p.axis, p.n, p.pcols, p.wide, st);
+        const bool pro = mode == MODE_CBS && i == 0;
+        if (pro && nstart == 0) continue;
+        const int kind = (mode == MODE_CBS && i == ps.count - 1) ? 5 : p.kind;
+        if (timed && timing_begin(*tp, group * 8 + (i == ps.count - 1 ? 4 : i), st) != hipSuccess)
+            return hipErrorUnknown;
+        hipError_t e = launch_pass<T>(kind, mode, pro ? starts : all, pro ? nstart : nall, g, p.axis, p.n, p.pcols,
+                                      p.wide, st);
         if (e != hipSuccess) return e;
+        if (timed && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
     }
-    return launch_reduce<T>(mode == MODE_CBS, dslots, ps.nparts, nslots, st);
+    if (timed && timing_begin(*tp, group * 8 + 5, st) != hipSuccess) return hipErrorUnknown;
+    hipError_t e = launch_reduce<T>(mode == MODE_CBS, all, ps.nparts, nall, st);
+    if (e != hipSuccess) return e;
+    if (timed && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_passes(cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T>* dslots, int nslots,
+                      hipStream_t st, bool start = true) {
+    return run_passes_set<T>(m->g, &m->timing, ps, mode, dslots, nslots, dslots, start ? nslots : 0, st);
+}
+
+// ------------------------------------------------------------ autotuner --
+// For every pass of an iteration, time the candidate FFT plans (the default
+// radix split, and the wider one with fewer elements per thread where it
+// exists) at every admissible tile width on the caller's workspace, and keep
+// the fastest.  Winners are cached per (shape, precision) for the process, so
+// every medium of one shape runs the same kernels (results of a solve do not
+// depend on which other solves ran first).  CBS_AUTOTUNE=0 keeps the defaults.
+struct TuneKey {
+    int ndim, n0, n1, n2, fp64;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(ndim, n0, n1, n2, fp64) < std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, PassSet> g_tune_cache;
+
+std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
+    std::vector<Pass> out;
+    const int last = g.ndim - 1;
+    const bool lastaxis = base.kind == 0 || base.kind == 1;
+    for (int wide = 0; wide < 2; ++wide) {
+        if (wide && !plan_has_wide(base.n)) continue;
+        const int tpc = plan_tpc(base.n, wide != 0);
+        int cap = 256 / tpc;
+        int64_t total;
+        if (lastaxis) {
+            total = g.ncell / g.n[last];
+            const size_t pencil_lds = (size_t)(base.n + base.n / 16) * (fp64 ? 16 : 8);
+            cap = std::min<int>(cap, (int)std::max<size_t>(1, (64 * 1024) / pencil_lds));
+        } else {
+            total = g.n[last];
+            cap = std::min(cap, fp64 ? 16 : 32);
+        }
+        for (int pc = 1; pc <= cap; pc *= 2) {
+            if (total % pc) break;
+            if (pc * tpc < 64 && pc * 2 <= cap && total % (pc * 2) == 0) continue;   // at least a wave
+            Pass p = base;
+            p.wide = wide != 0;
+            p.pcols = pc;
+            out.push_back(p);
+        }
+    }
+    return out;
+}
+
+template <typename T>
+float time_pass(cbs_medium_s* m, int kind, const Slot<T>* dslot, const Pass& p, hipStream_t st) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.f;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1.f;
+    }
+    float ms = -1.f;
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, st) == hipSuccess;
+    const int reps = 6;
+    ok = ok && hipEventRecord(a, st) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i)
+        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, st) == hipSuccess;
+    ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms /= reps;
+    else ms = -1.f;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+template <typename T>
+cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T>* w, cx<T>* y, Ctl* ctl,
+                    double* part, hipStream_t st) {
+    const int64_t nf = (int64_t)(m->g.ndim + 1) * m->g.ncell;
+    HIPOK(launch_zero<T>(x, nf, st));
+    HIPOK(launch_zero<T>(w, nf, st));
+    HIPOK(launch_zero<T>(y, nf, st));
+    HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+    Slot<T> h = make_slot<T>(m, x, w, y, ctl, part, 0, nullptr);
+    HIPOK(hipMemcpyAsync(dslot, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    HIPOK(hipStreamSynchronize(st));
+    const bool fp64 = sizeof(T) == 8;
+    for (int i = 0; i < ps.count; ++i) {
+        const int kind = (i == ps.count - 1) ? 5 : ps.p[i].kind;
+        float best = -1.f;
+        Pass pick = ps.p[i];
+        for (const Pass& c : pass_candidates(m->g, ps.p[i], fp64)) {
+            const float t = time_pass<T>(m, kind, dslot, c, st);
+            if (t > 0.f && (best < 0.f || t < best)) {
+                best = t;
+                pick = c;
+            }
+        }
+        ps.p[i] = pick;
+    }
+    const Pass& lp = ps.p[ps.count - 1];
+    ps.nparts = (int)((m->g.ndim + 1) * (m->g.ncell / ((int64_t)lp.n * lp.pcols)));
+    return CBS_OK;
 }
 
 struct Layout {
-    size_t off_slot64, off_ctl64, off_part64, off_x64, off_w64, off_y64;
-    size_t off_slot32, off_ctl32, off_part32, off_d32, off_w32, off_y32;
+    size_t off_slot64, off_ctl64, off_part64, off_chunk64, off_x64, off_w64, off_y64;
+    size_t off_slot32, off_ctl32, off_part32, off_chunk32, off_d32, off_w32, off_y32;
     size_t total;
 };
 
-Layout layout_for(const cbs_medium_s* m, int prec) {
+Layout layout_for(const Geom& g, int prec) {
     Layout L{};
-    const size_t nf = (size_t)(m->g.ndim + 1) * m->g.ncell;
+    const size_t nf = (size_t)(g.ndim + 1) * g.ncell;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -357,14 +545,19 @@ Layout layout_for(const cbs_medium_s* m, int prec) {
     };
     L.off_slot64 = take(sizeof(Slot<double>));
     L.off_ctl64 = take(sizeof(Ctl));
-    L.off_part64 = take(sizeof(double) * 2 * (size_t)std::max(m->ps64.nparts, 1));
+    // partial sums: one pair per work-group of the last pass, at any tile width
+    const size_t maxparts = (size_t)(g.ndim + 1) * (g.ncell / g.n[g.ndim - 1]);
+    const size_t maxchunks = (maxparts + kReduceChunk - 1) / kReduceChunk;
+    L.off_part64 = take(sizeof(double) * 2 * maxparts);
+    L.off_chunk64 = take(sizeof(double) * 2 * maxchunks);
     L.off_x64 = take(nf * sizeof(cx<double>));
     L.off_w64 = take(nf * sizeof(cx<double>));
     L.off_y64 = take(nf * sizeof(cx<double>));
     if (prec == CBS_FP32_REFINED) {
         L.off_slot32 = take(sizeof(Slot<float>));
         L.off_ctl32 = take(sizeof(Ctl));
-        L.off_part32 = take(sizeof(double) * 2 * (size_t)std::max(m->ps32.nparts, 1));
+        L.off_part32 = take(sizeof(double) * 2 * maxparts);
+        L.off_chunk32 = take(sizeof(double) * 2 * maxchunks);
         L.off_d32 = take(nf * sizeof(cx<float>));
         L.off_w32 = take(nf * sizeof(cx<float>));
         L.off_y32 = take(nf * sizeof(cx<float>));
@@ -373,9 +566,55 @@ Layout layout_for(const cbs_medium_s* m, int prec) {
     return L;
 }
 
+Layout layout_for(const cbs_medium_s* m, int prec) { return layout_for(m->g, prec); }
+
 template <typename T>
 T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+
+bool autotune_enabled() {
+    const char* e = std::getenv("CBS_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
+// Tune the pass sets this precision uses, on the caller's workspace (its
+// contents are scratch here), or take them from the process cache.
+cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
+    if (!autotune_enabled()) return CBS_OK;
+    const Layout L = layout_for(m, prec);
+    const Geom& g = m->g;
+    for (int fp64 = 1; fp64 >= 0; --fp64) {
+        if (!fp64 && prec != CBS_FP32_REFINED) continue;
+        bool& done = fp64 ? m->tuned64 : m->tuned32;
+        if (done) continue;
+        PassSet& ps = fp64 ? m->ps64 : m->ps32;
+        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                ps = it->second;
+                done = true;
+                continue;
+            }
+        }
+        cbs_status cs;
+        if (fp64)
+            cs = tune_set<double>(m, ps, at<Slot<double>>(ws, L.off_slot64), at<cx<double>>(ws, L.off_x64),
+                                  at<cx<double>>(ws, L.off_w64), at<cx<double>>(ws, L.off_y64),
+                                  at<Ctl>(ws, L.off_ctl64), at<double>(ws, L.off_part64), st);
+        else
+            cs = tune_set<float>(m, ps, at<Slot<float>>(ws, L.off_slot32), at<cx<float>>(ws, L.off_d32),
+                                 at<cx<float>>(ws, L.off_w32), at<cx<float>>(ws, L.off_y32),
+                                 at<Ctl>(ws, L.off_ctl32), at<double>(ws, L.off_part32), st);
+        if (cs != CBS_OK) return cs;
+        done = true;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = ps;
+    }
+    return CBS_OK;
 }
 
 cbs_status validate_grid(const cbs_grid* g) {
@@ -616,6 +855,7 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
 
 cbs_status cbs_destroy_medium(cbs_medium m) {
     if (!m) return CBS_E_INVALID;
+    for (hipEvent_t e : m->timing.ev) (void)hipEventDestroy(e);
     if (m->dev) (void)hipFree(m->dev);
     delete m;
     return CBS_OK;
@@ -697,9 +937,10 @@ cbs_status write_outputs(const cbs_medium_s* m, const cx<T>* x, void* p_out, voi
     return CBS_OK;
 }
 
-cbs_status read_ctl(const Ctl* d, Ctl* h, hipStream_t st) {
+cbs_status read_ctl(cbs_medium_s* m, const Ctl* d, Ctl* h, hipStream_t st) {
     HIPOK(hipMemcpyAsync(h, d, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIPOK(hipStreamSynchronize(st));
+    if (m->timing.on) timing_harvest(m->timing);
     return CBS_OK;
 }
 
@@ -717,6 +958,8 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
     const Geom& g = m->g;
     const int64_t nf = (int64_t)(g.ndim + 1) * g.ncell;
     const int check = o->check_every > 0 ? o->check_every : 32;
+    cbs_status ts = ensure_tuned(m, o->prec, ws, st);
+    if (ts != CBS_OK) return ts;
 
     Slot<double>* dslot64 = at<Slot<double>>(ws, L.off_slot64);
     Ctl* ctl64 = at<Ctl>(ws, L.off_ctl64);
@@ -733,7 +976,7 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
                      1.0 / std::sqrt(m->lam2), y64, nullptr, st));
     HIPOK(launch_zero<double>(x64, nf, st));
     HIPOK(hipMemsetAsync(ctl64, 0, sizeof(Ctl), st));
-    Slot<double> h64 = make_slot<double>(m, x64, w64, y64, ctl64, part64, adjoint);
+    Slot<double> h64 = make_slot<double>(m, x64, w64, y64, ctl64, part64, adjoint, at<double>(ws, L.off_chunk64));
     HIPOK(hipMemcpyAsync(dslot64, &h64, sizeof(h64), hipMemcpyHostToDevice, st));
 
     cbs_solve_info inf{};
@@ -745,15 +988,23 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
         const bool by_res = o->stop_rule == CBS_STOP_RESIDUAL;
         HIPOK(launch_ctl_reset(ctl64, (int)o->max_iter, by_res ? -1.0 : o->tol, st));
         int64_t launched = 0;
+        // the fused pass leaves the next iteration's transformed B x + y in w;
+        // a residual evaluation reuses w, so the iteration after it restarts
+        // from the stand-alone prologue pass
+        bool start = true;
         while (true) {
             const int64_t chunk = std::min<int64_t>(check, o->max_iter - launched);
-            for (int64_t k = 0; k < chunk; ++k) HIPOK(run_passes<double>(m, m->ps64, MODE_CBS, dslot64, 1, st));
+            for (int64_t k = 0; k < chunk; ++k) {
+                HIPOK(run_passes<double>(m, m->ps64, MODE_CBS, dslot64, 1, st, start));
+                start = false;
+            }
             launched += chunk;
             if (by_res) {
                 HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st));
                 inf.residual_evals++;
+                start = true;
             }
-            if ((cs = read_ctl(ctl64, &hc, st)) != CBS_OK) return cs;
+            if ((cs = read_ctl(m, ctl64, &hc, st)) != CBS_OK) return cs;
             inf.iterations = hc.iter;
             inf.rel_update = hc.rel_update;
             if (by_res) {
@@ -793,7 +1044,7 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
         cx<float>* y32 = at<cx<float>>(ws, L.off_y32);
         double* part32 = at<double>(ws, L.off_part32);
         HIPOK(hipMemsetAsync(ctl32, 0, sizeof(Ctl), st));
-        Slot<float> h32 = make_slot<float>(m, d32, w32, y32, ctl32, part32, adjoint);
+        Slot<float> h32 = make_slot<float>(m, d32, w32, y32, ctl32, part32, adjoint, at<double>(ws, L.off_chunk32));
         HIPOK(hipMemcpyAsync(dslot32, &h32, sizeof(h32), hipMemcpyHostToDevice, st));
         const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
         const int max_outer = o->max_outer > 0 ? o->max_outer : 50;
@@ -802,7 +1053,7 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
         for (int outer = 0;; ++outer) {
             HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st));
             inf.residual_evals++;
-            if ((cs = read_ctl(ctl64, &hc, st)) != CBS_OK) return cs;
+            if ((cs = read_ctl(m, ctl64, &hc, st)) != CBS_OK) return cs;
             inf.rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
             inf.outer = outer;
             if (!std::isfinite(inf.rel_residual)) {
@@ -825,9 +1076,10 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
             int64_t launched = 0;
             while (true) {
                 const int64_t chunk = std::min<int64_t>(check, cap - launched);
-                for (int64_t k = 0; k < chunk; ++k) HIPOK(run_passes<float>(m, m->ps32, MODE_CBS, dslot32, 1, st));
+                for (int64_t k = 0; k < chunk; ++k)
+                    HIPOK(run_passes<float>(m, m->ps32, MODE_CBS, dslot32, 1, st, launched + k == 0));
                 launched += chunk;
-                if ((cs = read_ctl(ctl32, &ic, st)) != CBS_OK) return cs;
+                if ((cs = read_ctl(m, ctl32, &ic, st)) != CBS_OK) return cs;
                 if (ic.done != RUNNING || launched >= cap) break;
             }
             total += ic.iter;
@@ -877,6 +1129,8 @@ cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const vo
     const Geom& g = m->g;
     const int64_t N = g.ncell;
     const int D = g.ndim;
+    cbs_status ts = ensure_tuned(m, CBS_FP64, workspace, st);
+    if (ts != CBS_OK) return ts;
     Slot<double>* dslot = at<Slot<double>>(workspace, L.off_slot64);
     Ctl* ctl = at<Ctl>(workspace, L.off_ctl64);
     cx<double>* x = at<cx<double>>(workspace, L.off_x64);
@@ -894,11 +1148,11 @@ cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const vo
     if (cs != CBS_OK) return cs;
     HIPOK(launch_scale_in(g, dp, du, std::sqrt(m->lam1), std::sqrt(m->lam2), x, st));
     HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
-    Slot<double> h = make_slot<double>(m, x, w, y, ctl, part, adjoint ? 1 : 0);
+    Slot<double> h = make_slot<double>(m, x, w, y, ctl, part, adjoint ? 1 : 0, at<double>(workspace, L.off_chunk64));
     HIPOK(hipMemcpyAsync(dslot, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot, 1, st));
     Ctl hc{};
-    if ((cs = read_ctl(ctl, &hc, st)) != CBS_OK) return cs;
+    if ((cs = read_ctl(m, ctl, &hc, st)) != CBS_OK) return cs;
     if (rel_residual) *rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
     if (r_p || r_u) {
         const double sl1 = std::sqrt(m->lam1), sl2 = std::sqrt(m->lam2);
@@ -976,5 +1230,344 @@ cbs_status cbs_gradient(cbs_medium m, const void* s_p, const void* s_u, const vo
     return rc;
 }
 
+cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]) {
+    if (!m || !out) return CBS_E_INVALID;
+    const PassSet& ps = prec == CBS_FP64 ? m->ps64 : m->ps32;
+    for (int i = 0; i < 5; ++i) {
+        const bool have = i < ps.count;
+        out[4 * i + 0] = have ? ps.p[i].kind : -1;
+        out[4 * i + 1] = have ? ps.p[i].n : 0;
+        out[4 * i + 2] = have ? ps.p[i].pcols : 0;
+        out[4 * i + 3] = have ? (ps.p[i].wide ? 1 : 0) : 0;
+    }
+    return CBS_OK;
+}
+
+cbs_status cbs_pass_timing(cbs_medium m, int32_t enable) {
+    if (!m) return CBS_E_INVALID;
+    PassTiming& t = m->timing;
+    if (enable) {
+        std::memset(t.ms, 0, sizeof(t.ms));
+        std::memset(t.cnt, 0, sizeof(t.cnt));
+        t.used = 0;
+    }
+    t.on = enable != 0;
+    return CBS_OK;
+}
+
+cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18]) {
+    if (!m || !ms || !launches) return CBS_E_INVALID;
+    for (int g = 0; g < 3; ++g)
+        for (int k = 0; k < 6; ++k) {
+            ms[g * 6 + k] = m->timing.ms[g][k];
+            launches[g * 6 + k] = m->timing.cnt[g][k];
+        }
+    return CBS_OK;
+}
+
 // batched slots: implemented in cbs_batch.cpp
+}  // extern "C"
+
+// =================================================== batched slots ======
+// Continuous batching of same-shape solves.  Each slot owns a region laid out
+// exactly like a single solve's workspace; its kernels, plans and
+// refinement steps are the ones cbs_solve runs, and a slot's arithmetic never
+// reads another slot's data, so its result is the same alone or in a mix.
+namespace {
+
+enum Phase { PH_FREE = 0, PH_RES = 1, PH_CBS = 2, PH_DONE = 3 };
+
+struct BatchSlot {
+    int phase = PH_FREE;
+    cbs_medium_s* m = nullptr;
+    cbs_solve_opts o{};
+    bool start = true;
+    int status = CBS_NOT_CONVERGED;
+    int64_t iters = 0, res_evals = 0;
+    int outer = 0;
+    double rel_res = -1.0, rel_upd = 0.0, t0 = 0.0;
+    Slot<double> h64{};
+    Slot<float> h32{};
+};
+
+}  // namespace
+
+struct cbs_batch_s {
+    Geom g{};
+    int prec = 0, maxs = 0;
+    char* ws = nullptr;
+    size_t header = 0, slot_bytes = 0;
+    Layout L{};
+    hipStream_t st = nullptr;
+    PassSet ps64{}, ps32{};
+    bool have_plans = false;
+    std::vector<BatchSlot> s;
+    Slot<double>* dc64 = nullptr;   // device: [0, maxs) all, [maxs, 2 maxs) starts
+    Slot<float>* dc32 = nullptr;
+    Slot<double>* hc64 = nullptr;   // pinned staging of the same
+    Slot<float>* hc32 = nullptr;
+    Ctl* hctl = nullptr;            // pinned: one control block per slot
+    char* region(int i) const { return ws + header + (size_t)i * slot_bytes; }
+};
+
+namespace {
+
+cbs_status batch_geom(const cbs_grid* grid, Geom* g) {
+    cbs_status vs = validate_grid(grid);
+    if (vs != CBS_OK) return vs;
+    g->ndim = grid->ndim;
+    g->ncell = 1;
+    for (int d = 0; d < 3; ++d) g->n[d] = d < grid->ndim ? (int)grid->n[d] : 1;
+    for (int d = 0; d < grid->ndim; ++d) g->ncell *= g->n[d];
+    return CBS_OK;
+}
+
+size_t batch_header(int maxs) {
+    return align_up(2 * (size_t)maxs * sizeof(Slot<double>)) + align_up(2 * (size_t)maxs * sizeof(Slot<float>));
+}
+
+cbs_status batch_residual_phase(cbs_batch_s* b) {
+    std::vector<int> idx;
+    for (int i = 0; i < b->maxs; ++i)
+        if (b->s[i].phase == PH_RES) idx.push_back(i);
+    if (idx.empty()) return CBS_OK;
+    const int n = (int)idx.size();
+    for (int k = 0; k < n; ++k) b->hc64[k] = b->s[idx[k]].h64;
+    HIPOK(hipMemcpyAsync(b->dc64, b->hc64, sizeof(Slot<double>) * n, hipMemcpyHostToDevice, b->st));
+    HIPOK(run_passes_set<double>(b->g, nullptr, b->ps64, MODE_APPLY, b->dc64, n, b->dc64, 0, b->st));
+    for (int k = 0; k < n; ++k)
+        HIPOK(hipMemcpyAsync(&b->hctl[idx[k]], b->s[idx[k]].h64.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, b->st));
+    HIPOK(hipStreamSynchronize(b->st));
+    const int64_t nf = (int64_t)(b->g.ndim + 1) * b->g.ncell;
+    for (int i : idx) {
+        BatchSlot& sl = b->s[i];
+        const Ctl& c = b->hctl[i];
+        sl.res_evals++;
+        sl.rel_res = c.rhs2 > 0 ? std::sqrt(c.res2 / c.rhs2) : 0.0;
+        const int max_outer = sl.o.max_outer > 0 ? sl.o.max_outer : 50;
+        if (!std::isfinite(sl.rel_res)) {
+            sl.status = CBS_E_DIVERGED;
+            sl.phase = PH_DONE;
+        } else if (sl.rel_res <= sl.o.tol) {
+            sl.status = CBS_OK;
+            sl.phase = PH_DONE;
+        } else if (sl.outer >= max_outer || sl.iters >= sl.o.max_iter) {
+            sl.status = CBS_NOT_CONVERGED;
+            sl.phase = PH_DONE;
+        } else {
+            const double inner_tol = sl.o.inner_tol > 0 ? sl.o.inner_tol : 1e-3;
+            HIPOK(launch_convert(sl.h64.w, const_cast<cx<float>*>(sl.h32.y), nf, sl.h64.ctl, b->st));
+            HIPOK(launch_zero<float>(sl.h32.x, nf, b->st));
+            HIPOK(launch_ctl_reset(sl.h32.ctl, (int)(sl.o.max_iter - sl.iters), inner_tol, b->st));
+            sl.phase = PH_CBS;
+            sl.start = true;
+        }
+    }
+    return CBS_OK;
+}
+
+template <typename T>
+cbs_status batch_cbs_phase(cbs_batch_s* b, int iterations, Slot<T>* dc, Slot<T>* hc, const PassSet& ps) {
+    std::vector<int> idx, starts;
+    for (int i = 0; i < b->maxs; ++i)
+        if (b->s[i].phase == PH_CBS) {
+            idx.push_back(i);
+            if (b->s[i].start) starts.push_back(i);
+        }
+    if (idx.empty()) return CBS_OK;
+    const int n = (int)idx.size(), ns = (int)starts.size();
+    auto desc = [&](int i) -> const Slot<T>& {
+        if constexpr (sizeof(T) == 8) return b->s[i].h64;
+        else return b->s[i].h32;
+    };
+    for (int k = 0; k < n; ++k) hc[k] = desc(idx[k]);
+    for (int k = 0; k < ns; ++k) hc[b->maxs + k] = desc(starts[k]);
+    HIPOK(hipMemcpyAsync(dc, hc, sizeof(Slot<T>) * n, hipMemcpyHostToDevice, b->st));
+    if (ns) HIPOK(hipMemcpyAsync(dc + b->maxs, hc + b->maxs, sizeof(Slot<T>) * ns, hipMemcpyHostToDevice, b->st));
+    for (int it = 0; it < iterations; ++it)
+        HIPOK(run_passes_set<T>(b->g, nullptr, ps, MODE_CBS, dc, n, dc + b->maxs, it == 0 ? ns : 0, b->st));
+    for (int i : idx) {
+        b->s[i].start = false;
+        HIPOK(hipMemcpyAsync(&b->hctl[i], desc(i).ctl, sizeof(Ctl), hipMemcpyDeviceToHost, b->st));
+    }
+    HIPOK(hipStreamSynchronize(b->st));
+    const int64_t nf = (int64_t)(b->g.ndim + 1) * b->g.ncell;
+    for (int i : idx) {
+        BatchSlot& sl = b->s[i];
+        const Ctl& c = b->hctl[i];
+        if (c.done == RUNNING) continue;
+        sl.rel_upd = c.rel_update;
+        if (b->prec == CBS_FP64) {
+            sl.iters = c.iter;
+            sl.status = c.done == CONVERGED ? CBS_OK : (c.done == DIVERGED ? CBS_E_DIVERGED : CBS_NOT_CONVERGED);
+            sl.phase = PH_DONE;
+        } else {
+            sl.iters += c.iter;
+            if (c.done == DIVERGED) {
+                sl.status = CBS_E_DIVERGED;
+                sl.phase = PH_DONE;
+            } else {
+                HIPOK(launch_accumulate(sl.h64.x, sl.h32.x, nf, sl.h64.ctl, b->st));
+                sl.outer++;
+                sl.phase = PH_RES;
+            }
+        }
+    }
+    return CBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cbs_status cbs_batch_workspace_bytes(const cbs_grid* grid, int32_t prec, int32_t max_slots, size_t* bytes) {
+    if (!bytes || max_slots < 1 || max_slots > 4096) return CBS_E_INVALID;
+    if (prec != CBS_FP64 && prec != CBS_FP32_REFINED) return CBS_E_INVALID;
+    Geom g{};
+    cbs_status cs = batch_geom(grid, &g);
+    if (cs != CBS_OK) return cs;
+    *bytes = batch_header(max_slots) + (size_t)max_slots * layout_for(g, prec).total;
+    return CBS_OK;
+}
+
+cbs_status cbs_batch_create(const cbs_grid* grid, int32_t prec, int32_t max_slots, void* workspace,
+                            size_t ws_bytes, void* hip_stream, cbs_batch* out) {
+    if (!out || !workspace) return CBS_E_INVALID;
+    *out = nullptr;
+    size_t need = 0;
+    cbs_status cs = cbs_batch_workspace_bytes(grid, prec, max_slots, &need);
+    if (cs != CBS_OK) return cs;
+    if (ws_bytes < need) return CBS_E_NOMEM;
+    cbs_batch_s* b = new (std::nothrow) cbs_batch_s();
+    if (!b) return CBS_E_NOMEM;
+    batch_geom(grid, &b->g);
+    b->prec = prec;
+    b->maxs = max_slots;
+    b->ws = static_cast<char*>(workspace);
+    b->st = (hipStream_t)hip_stream;
+    b->L = layout_for(b->g, prec);
+    b->slot_bytes = b->L.total;
+    b->header = batch_header(max_slots);
+    b->s.resize(max_slots);
+    b->dc64 = reinterpret_cast<Slot<double>*>(b->ws);
+    b->dc32 = reinterpret_cast<Slot<float>*>(b->ws + align_up(2 * (size_t)max_slots * sizeof(Slot<double>)));
+    if (hipHostMalloc((void**)&b->hc64, 2 * sizeof(Slot<double>) * max_slots) != hipSuccess ||
+        hipHostMalloc((void**)&b->hc32, 2 * sizeof(Slot<float>) * max_slots) != hipSuccess ||
+        hipHostMalloc((void**)&b->hctl, sizeof(Ctl) * max_slots) != hipSuccess) {
+        cbs_batch_destroy(b);
+        return CBS_E_NOMEM;
+    }
+    *out = b;
+    return CBS_OK;
+}
+
+cbs_status cbs_batch_destroy(cbs_batch b) {
+    if (!b) return CBS_E_INVALID;
+    (void)hipStreamSynchronize(b->st);
+    if (b->hc64) (void)hipHostFree(b->hc64);
+    if (b->hc32) (void)hipHostFree(b->hc32);
+    if (b->hctl) (void)hipHostFree(b->hctl);
+    delete b;
+    return CBS_OK;
+}
+
+cbs_status cbs_batch_submit(cbs_batch b, cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* o,
+                            int32_t* slot) {
+    if (!b || !m || !s_p || !o || !slot) return CBS_E_INVALID;
+    if (o->prec != b->prec) return CBS_E_INVALID;
+    if (o->ptr_kind != CBS_PTR_HOST && o->ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    if (o->rhs_kind != CBS_RHS_PHYSICAL && o->rhs_kind != CBS_RHS_EQUATION) return CBS_E_INVALID;
+    if (!(o->tol >= 0) || o->max_iter < 1 || o->max_iter > 0x7fffffff) return CBS_E_INVALID;
+    if (b->prec == CBS_FP64 && o->stop_rule != CBS_STOP_UPDATE) return CBS_E_UNSUPPORTED;
+    for (int d = 0; d < 3; ++d)
+        if (m->g.n[d] != b->g.n[d] || m->g.ndim != b->g.ndim) return CBS_E_INVALID;
+    int i = 0;
+    while (i < b->maxs && b->s[i].phase != PH_FREE) ++i;
+    if (i == b->maxs) return CBS_E_NOMEM;
+    char* ws = b->region(i);
+    if (!b->have_plans) {
+        cbs_status ts = ensure_tuned(m, b->prec, ws, b->st);
+        if (ts != CBS_OK) return ts;
+        b->ps64 = m->ps64;
+        b->ps32 = m->ps32;
+        b->have_plans = true;
+    }
+    const Layout& L = b->L;
+    const Geom& g = b->g;
+    const int64_t nf = (int64_t)(g.ndim + 1) * g.ncell;
+    BatchSlot& sl = b->s[i];
+    sl = BatchSlot();
+    sl.t0 = now_s();
+    sl.m = m;
+    sl.o = *o;
+    cx<double>* x64 = at<cx<double>>(ws, L.off_x64);
+    cx<double>* w64 = at<cx<double>>(ws, L.off_w64);
+    cx<double>* y64 = at<cx<double>>(ws, L.off_y64);
+    const cx<double>*dsp = nullptr, *dsu = nullptr;
+    cbs_status cs = stage_sources(m, s_p, s_u, o->ptr_kind, w64, &dsp, &dsu, b->st);
+    if (cs != CBS_OK) return cs;
+    HIPOK(launch_rhs(g, dsp, dsu, m->rhobar64, m->q64, o->rhs_kind == CBS_RHS_PHYSICAL, 1.0 / std::sqrt(m->lam1),
+                     1.0 / std::sqrt(m->lam2), y64, nullptr, b->st));
+    HIPOK(launch_zero<double>(x64, nf, b->st));
+    Ctl* ctl64 = at<Ctl>(ws, L.off_ctl64);
+    HIPOK(hipMemsetAsync(ctl64, 0, sizeof(Ctl), b->st));
+    sl.h64 = make_slot<double>(m, x64, w64, y64, ctl64, at<double>(ws, L.off_part64), 0,
+                               at<double>(ws, L.off_chunk64));
+    if (b->prec == CBS_FP32_REFINED) {
+        Ctl* ctl32 = at<Ctl>(ws, L.off_ctl32);
+        HIPOK(hipMemsetAsync(ctl32, 0, sizeof(Ctl), b->st));
+        sl.h32 = make_slot<float>(m, at<cx<float>>(ws, L.off_d32), at<cx<float>>(ws, L.off_w32),
+                                  at<cx<float>>(ws, L.off_y32), ctl32, at<double>(ws, L.off_part32), 0,
+                                  at<double>(ws, L.off_chunk32));
+        sl.phase = PH_RES;
+    } else {
+        HIPOK(launch_ctl_reset(ctl64, (int)o->max_iter, o->tol, b->st));
+        sl.phase = PH_CBS;
+        sl.start = true;
+    }
+    *slot = i;
+    return CBS_OK;
+}
+
+cbs_status cbs_batch_step(cbs_batch b, int32_t iterations, uint8_t* done_mask) {
+    if (!b || iterations < 1) return CBS_E_INVALID;
+    cbs_status cs = CBS_OK;
+    if (b->prec == CBS_FP32_REFINED) {
+        if ((cs = batch_residual_phase(b)) != CBS_OK) return cs;
+        cs = batch_cbs_phase<float>(b, iterations, b->dc32, b->hc32, b->ps32);
+    } else {
+        cs = batch_cbs_phase<double>(b, iterations, b->dc64, b->hc64, b->ps64);
+    }
+    if (cs != CBS_OK) return cs;
+    if (done_mask)
+        for (int i = 0; i < b->maxs; ++i) done_mask[i] = b->s[i].phase == PH_DONE ? 1 : 0;
+    return CBS_OK;
+}
+
+cbs_status cbs_batch_retire(cbs_batch b, int32_t slot, void* p_out, void* u_out, int32_t ptr_kind,
+                            cbs_solve_info* info) {
+    if (!b || slot < 0 || slot >= b->maxs) return CBS_E_INVALID;
+    BatchSlot& sl = b->s[slot];
+    if (sl.phase != PH_DONE) return CBS_E_INVALID;
+    if (ptr_kind != CBS_PTR_HOST && ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    if (sl.status != CBS_E_DIVERGED && p_out) {
+        cbs_status cs = write_outputs<double>(sl.m, sl.h64.x, p_out, u_out, ptr_kind, sl.h64.w, b->st);
+        if (cs != CBS_OK) return cs;
+    }
+    if (info) {
+        cbs_solve_info inf{};
+        inf.iterations = sl.iters;
+        inf.outer = sl.outer;
+        inf.status = sl.status;
+        inf.rel_update = sl.rel_upd;
+        inf.rel_residual = sl.rel_res;
+        inf.seconds = now_s() - sl.t0;
+        inf.residual_evals = sl.res_evals;
+        *info = inf;
+    }
+    const int st = sl.status;
+    sl = BatchSlot();
+    return (cbs_status)st;
+}
+
 }  // extern "C"

@@ -26,7 +26,7 @@ struct Ctl {
     double rhs2;         // |y|^2 of the last residual evaluation
     double scale;        // |r| used by the refinement convert/accumulate kernels
     int res_done;        // residual evaluations since reset
-    int pad;
+    int arrive;          // blocks of the current reduction that have finished
 };
 
 enum Done { RUNNING = 0, CONVERGED = 1, CAPPED = 2, DIVERGED = 3 };
@@ -58,7 +58,11 @@ struct Slot {
     int pad;
     Ctl* ctl;
     double* partials;     // 2 doubles per work-group of the last pass
+    double* chunks;       // 2 doubles per block of the reduction
 };
+
+// Partial-sum pairs one reduction block folds.
+constexpr int kReduceChunk = 4096;
 
 struct Geom {
     int ndim;

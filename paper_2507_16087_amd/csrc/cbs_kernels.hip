@@ -27,6 +27,7 @@
 // propagator costs no extra LDS or HBM traffic.
 #include "cbs_internal.h"
 
+#include <algorithm>
 #include <utility>
 
 namespace cbs {
@@ -204,17 +205,31 @@ struct Seq {
     }
 };
 
-// LDS tile: element n of column c at lds[n * ldp + c].
-template <int N, int R, int TPC, typename T>
+// LDS tile layouts.  COLS (column-fastest threads): element n of column c at
+// lds[n * ldp + c], so a wave's columns hit consecutive words.  ROWS
+// (lane-fastest threads): lds[c * ldp + n + n / 16], the pad word every 16
+// elements keeping the stride-R Stockham scatters off a single bank.
+enum Lay { COLS = 0, ROWS = 1 };
+template <int LAY>
+__device__ __forceinline__ int lidx(int n, int col, int ldp) {
+    if constexpr (LAY == COLS) return n * ldp + col;
+    else return col * ldp + n + (n >> 4);
+}
+template <int LAY>
+constexpr int lds_pitch(int n, int pcols) {
+    return LAY == COLS ? pcols + 1 : n + n / 16;
+}
+
+template <int N, int R, int TPC, int LAY, typename T>
 __device__ __forceinline__ void lds_gather(cx<T>* v, const cx<T>* lds, int ldp, int col, int lane) {
     constexpr int NB = N / (R * TPC);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b * R + r] = lds[(lane + b * TPC + r * (N / R)) * ldp + col];
+        for (int r = 0; r < R; ++r) v[b * R + r] = lds[lidx<LAY>(lane + b * TPC + r * (N / R), col, ldp)];
 }
 
-template <int N, int R, int Ns, int TPC, typename T>
+template <int N, int R, int Ns, int TPC, int LAY, typename T>
 __device__ __forceinline__ void lds_scatter(const cx<T>* v, cx<T>* lds, int ldp, int col, int lane) {
     constexpr int NB = N / (R * TPC);
 #pragma unroll
@@ -222,7 +237,7 @@ __device__ __forceinline__ void lds_scatter(const cx<T>* v, cx<T>* lds, int ldp,
         const int j = lane + b * TPC;
         const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ldp + col] = v[b * R + r];
+        for (int r = 0; r < R; ++r) lds[lidx<LAY>(base + r * Ns, col, ldp)] = v[b * R + r];
     }
 }
 
@@ -248,23 +263,23 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int lane, const cx<T>* _
 // (elements lane + b TPC + r N/R); on exit v holds the outputs of the last
 // stage, element lane + b TPC + r N/R_last in natural order.  The LDS tile
 // must be free on entry; it is still being read on exit.
-template <class P, int DIR, typename T>
+template <class P, int DIR, int LAY = COLS, typename T>
 __device__ __forceinline__ void fft_regs(cx<T>* v, cx<T>* lds, int ldp, int col, int lane,
                                          const cx<T>* __restrict__ tw) {
     using Q = Seq<P, DIR>;
     constexpr int N = P::N, TPC = P::TPC;
     stage_compute<N, Q::r(0), 1, TPC, DIR>(v, lane, tw);
     if constexpr (P::S >= 2) {
-        lds_scatter<N, Q::r(0), 1, TPC>(v, lds, ldp, col, lane);
+        lds_scatter<N, Q::r(0), 1, TPC, LAY>(v, lds, ldp, col, lane);
         __syncthreads();
-        lds_gather<N, Q::r(1), TPC>(v, lds, ldp, col, lane);
+        lds_gather<N, Q::r(1), TPC, LAY>(v, lds, ldp, col, lane);
         stage_compute<N, Q::r(1), Q::ns(1), TPC, DIR>(v, lane, tw);
     }
     if constexpr (P::S >= 3) {
         __syncthreads();
-        lds_scatter<N, Q::r(1), Q::ns(1), TPC>(v, lds, ldp, col, lane);
+        lds_scatter<N, Q::r(1), Q::ns(1), TPC, LAY>(v, lds, ldp, col, lane);
         __syncthreads();
-        lds_gather<N, Q::r(2), TPC>(v, lds, ldp, col, lane);
+        lds_gather<N, Q::r(2), TPC, LAY>(v, lds, ldp, col, lane);
         stage_compute<N, Q::r(2), Q::ns(2), TPC, DIR>(v, lane, tw);
     }
 }
@@ -279,6 +294,14 @@ template <class P, int DIR>
 __device__ __forceinline__ int in_index(int lane, int b, int r) {
     constexpr int R0 = Seq<P, DIR>::r(0);
     return lane + b * P::TPC + r * (P::N / R0);
+}
+
+// Per-work-group copies of the small per-axis tables (FFT twiddles, layer
+// profile, wavenumbers) live in LDS after the tile, so the FFT stages and the
+// fused prologue / epilogue read them without touching the vector memory path.
+template <typename T>
+__host__ __device__ __forceinline__ size_t tile_bytes(size_t elems) {
+    return (elems * sizeof(cx<T>) + 15) & ~size_t(15);
 }
 
 // ------------------------------------------------- medium on the fly --
@@ -362,87 +385,139 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
     }
 }
 
-// ------------------------------------------- pass A / E: contiguous axis --
-// Tile = P consecutive pencils along the last axis (one contiguous run of
-// P * N cells).  grid = (tiles, F, slots); block = P * TPC threads.
-// FIRST: prologue (CBS: w = B x + y; APPLY: w = x), forward FFT, store w.
-// !FIRST: load w, inverse FFT, epilogue (CBS: x += nu B (z - x) with norm
-// partials; APPLY: w = y - D x / lam - z with |r|^2, |y|^2 partials).
-template <class P, int MODE, bool FIRST, typename T>
-__global__ void __launch_bounds__(256) k_contig(const Slot<T>* __restrict__ slots, Geom g, int pcols,
-                                                int ldp) {
+// --------------------------------- passes A / E: last (contiguous) axis --
+// One work-group owns P whole pencils of one field; TPC lane-fastest threads
+// per pencil, so each stage-0 load and last-stage store of a pencil is one
+// contiguous run.  grid = (pencils / P, F, slots).
+//   KIND FIRST : prologue (CBS: w = B x + y; APPLY: w = x) -> forward FFT -> w
+//   KIND LAST  : w -> inverse FFT -> epilogue (CBS: x += nu B (z - x) with
+//                |dx|^2, |x|^2 partials; APPLY: w = y - D x / lam - z with
+//                |r|^2, |y|^2 partials)
+//   KIND FUSED : LAST's CBS epilogue, then the next iteration's prologue on
+//                the same registers, forward FFT -> w.  The inverse transform
+//                (radices reversed) leaves each thread holding exactly the
+//                elements the forward transform's first stage needs.
+enum Kind { FIRST = 0, LAST = 1, FUSED = 2 };
+
+template <class P, int MODE, int KIND, typename T>
+__global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ slots, Geom g, int pcols) {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
     if (MODE == CBS && s.ctl->done) return;
-    constexpr int N = P::N;
+    constexpr int N = P::N, E = P::E, TPC = P::TPC;
+    constexpr int ldp = lds_pitch<ROWS>(N, 0);
     const int f = blockIdx.y;
-    const int nthr = pcols * P::TPC;
+    const int D = g.ndim, last = D - 1;
     const int tid = threadIdx.x;
-    const int64_t tile0 = (int64_t)blockIdx.x * pcols * N;     // first cell of the tile
-    const int64_t plane = (int64_t)f * g.ncell;
-    const int tile_elems = pcols * N;
-    const int last = g.ndim - 1;
-    const cx<T>* __restrict__ tw = s.tw[last];
-
-    if constexpr (FIRST) {
-        for (int e = tid; e < tile_elems; e += nthr) {
-            const int64_t cell = tile0 + e;
-            cx<T> xv = s.x[plane + cell];
-            cx<T> wv;
-            if constexpr (MODE == CBS) {
-                int ix[3];
-                tile_coords<N>(g, blockIdx.x * pcols, e, ix);
-                wv = cmul(bval(s, g, f, cell, ix), xv) + s.y[plane + cell];
-            } else {
-                wv = xv;
-            }
-            lds[(e % N) * ldp + e / N] = wv;
+    const int lane = tid % TPC, col = tid / TPC;
+    const int pencil = blockIdx.x * pcols + col;
+    // uniform tile bases; per-thread 32-bit offsets (pl + n) inside the tile
+    const int64_t tile0 = (int64_t)blockIdx.x * pcols * N;
+    const int64_t fbase = (int64_t)f * g.ncell + tile0;
+    const uint32_t pl = (uint32_t)(col * N);
+    // LDS: tile | twiddles (N) | layer profile of the last axis (N)
+    // (the tile also hosts the 64-double block reduction, hence the floor)
+    const size_t tab_off = max(tile_bytes<T>((size_t)pcols * ldp), (size_t)(64 * sizeof(double)));
+    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tab_off);
+    T* prof_l = reinterpret_cast<T*>(tw_l + N);
+    {
+        const T* __restrict__ src = (f == last) ? s.gs[last] : s.gc[last];
+        for (int i = tid; i < N; i += blockDim.x) {
+            tw_l[i] = s.tw[last][i];
+            prof_l[i] = src[i];
         }
-    } else {
-        for (int e = tid; e < tile_elems; e += nthr) lds[(e % N) * ldp + e / N] = s.w[plane + tile0 + e];
     }
     __syncthreads();
+    const cx<T>* tw = tw_l;
+    cx<T>* __restrict__ w = s.w + fbase;
+    cx<T>* __restrict__ x = s.x + fbase;
+    const cx<T>* __restrict__ y = s.y + fbase;
 
-    const int col = tid % pcols, lane = tid / pcols;
-    constexpr int DIR = FIRST ? -1 : 1;
-    using Q = Seq<P, DIR>;
-    cx<T> v[P::E];
-    lds_gather<N, Q::r(0), P::TPC>(v, lds, ldp, col, lane);
-    __syncthreads();
-    fft_regs<P, DIR>(v, lds, ldp, col, lane, tw);
-    __syncthreads();
-    lds_scatter<N, Q::r(P::S - 1), Q::ns(P::S - 1), P::TPC>(v, lds, ldp, col, lane);
-    __syncthreads();
-
-    if constexpr (FIRST) {
-        for (int e = tid; e < tile_elems; e += nthr) s.w[plane + tile0 + e] = lds[(e % N) * ldp + e / N];
+    // per-pencil part of the layer rate for this field's row
+    int ix[3];
+    if (D == 3) {
+        ix[1] = pencil % g.n[1];
+        ix[0] = pencil / g.n[1];
     } else {
-        double acc0 = 0.0, acc1 = 0.0;
-        for (int e = tid; e < tile_elems; e += nthr) {
-            const int64_t cell = tile0 + e;
-            const cx<T> z = lds[(e % N) * ldp + e / N];
-            int ix[3];
-            tile_coords<N>(g, blockIdx.x * pcols, e, ix);
-            if constexpr (MODE == CBS) {
-                const cx<T> xv = s.x[plane + cell];
-                const cx<T> b = bval(s, g, f, cell, ix);
-                const cx<T> dxv = rmul(s.nu, cmul(b, z - xv));
-                s.x[plane + cell] = xv + dxv;
-                acc0 += (double)norm2(dxv);
-                acc1 += (double)norm2(xv);
-            } else {
-                const cx<T> xv = s.x[plane + cell];
-                const cx<T> yv = s.y[plane + cell];
-                const cx<T> D = diag_D(s, g, f, cell, ix);
-                const T il = f < g.ndim ? s.inv_lam1 : s.inv_lam2;
-                const cx<T> r = yv - rmul(il, cmul(D, xv)) - z;
-                s.w[plane + cell] = r;
-                acc0 += (double)norm2(r);
-                acc1 += (double)norm2(yv);
-            }
+        ix[0] = pencil;
+    }
+    T colsum = 0;
+    for (int d = 0; d < last; ++d) colsum += (d == f) ? s.gs[d][ix[d]] : s.gc[d][ix[d]];
+    const T* lastprof = prof_l;
+    const bool urow = f < D;
+    const T* __restrict__ rb = s.rhobar + (urow ? fbase : 0) + pl;
+    const cx<T>* __restrict__ qv = s.q + tile0 + pl;
+    const T are = urow ? s.a1re : s.a2re;
+    const T aim = s.adjoint ? -(urow ? s.a1im : s.a2im) : (urow ? s.a1im : s.a2im);
+    const T il = urow ? s.inv_lam1 : s.inv_lam2;
+    const T wim = s.adjoint ? -s.omega : s.omega;
+    // diagonal D (conjugated for the adjoint) at element n of the pencil
+    auto diag = [&](int n) -> cx<T> {
+        const T gam = s.gmax * (colsum + lastprof[n]);
+        if (urow) {
+            const T r = rb[n];
+            return {r * gam, r * wim};
         }
-        __syncthreads();
+        const cx<T> q = qv[n];
+        const cx<T> dd = {gam * q.re - s.omega * q.im, gam * q.im + s.omega * q.re};
+        return {dd.re, s.adjoint ? -dd.im : dd.im};
+    };
+
+    cx<T> v[E];
+    using QF = Seq<P, -1>;
+    using QI = Seq<P, 1>;
+    if constexpr (KIND == FIRST) {
+        constexpr int R0 = QF::r(0);
+#pragma unroll
+        for (int b = 0; b < N / (R0 * TPC); ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int n = in_index<P, -1>(lane, b, r);
+                const cx<T> xv = x[pl + n];
+                if constexpr (MODE == CBS) {
+                    const cx<T> dd = diag(n);
+                    const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
+                    v[b * R0 + r] = cmul(bb, xv) + y[pl + n];
+                } else {
+                    v[b * R0 + r] = xv;
+                }
+            }
+    } else {
+        constexpr int R0 = QI::r(0);
+#pragma unroll
+        for (int b = 0; b < N / (R0 * TPC); ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[b * R0 + r] = w[pl + in_index<P, 1>(lane, b, r)];
+        fft_regs<P, 1, ROWS>(v, lds, ldp, col, lane, tw);
+        double acc0 = 0.0, acc1 = 0.0;
+        constexpr int RL = QI::r(P::S - 1);   // == forward R0
+#pragma unroll
+        for (int b = 0; b < N / (RL * TPC); ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int n = out_index<P, 1>(lane, b, r);
+                const int e = b * RL + r;
+                const cx<T> z = v[e];
+                const cx<T> xv = x[pl + n];
+                const cx<T> dd = diag(n);
+                if constexpr (MODE == CBS) {
+                    const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
+                    const cx<T> dxv = rmul(s.nu, cmul(bb, z - xv));
+                    const cx<T> xn = xv + dxv;
+                    x[pl + n] = xn;
+                    acc0 += (double)norm2(dxv);
+                    acc1 += (double)norm2(xv);
+                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + y[pl + n];
+                } else {
+                    const cx<T> yv = y[pl + n];
+                    const cx<T> rr = yv - rmul(il, cmul(dd, xv)) - z;
+                    w[pl + n] = rr;
+                    acc0 += (double)norm2(rr);
+                    acc1 += (double)norm2(yv);
+                }
+            }
+        // work-group partial sums (the tile is free again after this)
         double* red = reinterpret_cast<double*>(smem_raw);
         block_sum2(acc0, acc1, red);
         if (tid == 0) {
@@ -450,7 +525,16 @@ __global__ void __launch_bounds__(256) k_contig(const Slot<T>* __restrict__ slot
             s.partials[2 * part] = acc0;
             s.partials[2 * part + 1] = acc1;
         }
+        if constexpr (KIND == LAST) return;
+        __syncthreads();
     }
+    // forward transform of the prepared registers, natural-order store
+    fft_regs<P, -1, ROWS>(v, lds, ldp, col, lane, tw);
+    constexpr int RLF = QF::r(P::S - 1);
+#pragma unroll
+    for (int b = 0; b < N / (RLF * TPC); ++b)
+#pragma unroll
+        for (int r = 0; r < RLF; ++r) w[pl + out_index<P, -1>(lane, b, r)] = v[b * RLF + r];
 }
 
 // ------------------------------------------- pass B / D: strided axis --
@@ -467,23 +551,28 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
     if (skip_done && s.ctl->done) return;
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
-    const int64_t base = (int64_t)blockIdx.y * g.ncell + (int64_t)(blockIdx.x / nlast_tiles) * ostride +
-                         (int64_t)(blockIdx.x % nlast_tiles) * pcols + col;
-    cx<T>* __restrict__ w = s.w;
+    cx<T>* __restrict__ w = s.w + (int64_t)blockIdx.y * g.ncell + (int64_t)(blockIdx.x / nlast_tiles) * ostride +
+                            (int64_t)(blockIdx.x % nlast_tiles) * pcols;
+    const uint32_t es32 = (uint32_t)es;
     cx<T> v[P::E];
     constexpr int NB0 = P::N / (Seq<P, DIR>::r(0) * P::TPC);
 #pragma unroll
     for (int b = 0; b < NB0; ++b)
 #pragma unroll
         for (int r = 0; r < Seq<P, DIR>::r(0); ++r)
-            v[b * Seq<P, DIR>::r(0) + r] = w[base + (int64_t)in_index<P, DIR>(lane, b, r) * es];
-    fft_regs<P, DIR>(v, lds, ldp, col, lane, s.tw[axis]);
+            v[b * Seq<P, DIR>::r(0) + r] = w[(uint32_t)col + (uint32_t)in_index<P, DIR>(lane, b, r) * es32];
+    // twiddles in LDS after the tile (first used after the first stage's barrier)
+    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tile_bytes<T>((size_t)P::N * ldp));
+    for (int i = tid; i < P::N; i += blockDim.x) tw_l[i] = s.tw[axis][i];
+    if constexpr (P::S == 1) __syncthreads();
+    fft_regs<P, DIR>(v, lds, ldp, col, lane, tw_l);
     constexpr int Rl = Seq<P, DIR>::r(P::S - 1);
     constexpr int NBl = P::N / (Rl * P::TPC);
 #pragma unroll
     for (int b = 0; b < NBl; ++b)
 #pragma unroll
-        for (int r = 0; r < Rl; ++r) w[base + (int64_t)out_index<P, DIR>(lane, b, r) * es] = v[b * Rl + r];
+        for (int r = 0; r < Rl; ++r)
+            w[(uint32_t)col + (uint32_t)out_index<P, DIR>(lane, b, r) * es32] = v[b * Rl + r];
 }
 
 // ------------------------------------- pass C: axis 0 with the propagator --
@@ -504,9 +593,19 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     const int col = tid % pcols, lane = tid / pcols;
     const int io = blockIdx.x / nlast_tiles;                       // index along the middle axis (3-D)
     const int il = (blockIdx.x % nlast_tiles) * pcols + col;       // index along the last axis
-    const int64_t base = (int64_t)io * ostride + il;
-    cx<T>* __restrict__ w = s.w;
-    const cx<T>* __restrict__ tw = s.tw[0];
+    cx<T>* __restrict__ wt = s.w + (int64_t)io * ostride + (int64_t)(blockIdx.x % nlast_tiles) * pcols;
+    const uint32_t es32 = (uint32_t)es;
+    // LDS: tile | twiddles (N) | k0 S0 (N) | k0 (N)
+    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tile_bytes<T>((size_t)N * ldp));
+    cx<T>* g0_l = tw_l + N;
+    T* k0_l = reinterpret_cast<T*>(g0_l + N);
+    for (int i = tid; i < N; i += blockDim.x) {
+        tw_l[i] = s.tw[0][i];
+        k0_l[i] = s.kv[0][i];
+        g0_l[i] = rmul(s.kv[0][i], s.sh[0][i]);
+    }
+    __syncthreads();
+    const cx<T>* tw = tw_l;
 
     // wavevector components of this column (axes 1.., FFT order)
     T kc[2];
@@ -525,16 +624,22 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
 
     cx<T> v[4][E];
     using QF = Seq<P, -1>;
+    // issue every field's loads before the first transform
+    constexpr int R0 = QF::r(0);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         if (f < F) {
-            const int64_t pb = (int64_t)f * g.ncell + base;
-            constexpr int R0 = QF::r(0);
+            const cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
 #pragma unroll
             for (int b = 0; b < N / (R0 * P::TPC); ++b)
 #pragma unroll
                 for (int r = 0; r < R0; ++r)
-                    v[f][b * R0 + r] = w[pb + (int64_t)in_index<P, -1>(lane, b, r) * es];
+                    v[f][b * R0 + r] = wf[(uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32];
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (f < F) {
             if (f > 0) __syncthreads();
             fft_regs<P, -1>(v[f], lds, ldp, col, lane, tw);
         }
@@ -549,8 +654,8 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
         for (int r = 0; r < Rl; ++r) {
             const int k0i = out_index<P, -1>(lane, b, r);
             const int e = b * Rl + r;
-            const T k0 = s.kv[0][k0i];
-            const cx<T> g0 = rmul(k0, s.sh[0][k0i]);
+            const T k0 = k0_l[k0i];
+            const cx<T> g0 = g0_l[k0i];
             cx<T> gg[3] = {g0, gc[0], gc[1]};
             const cx<T> wp = (D == 3) ? v[3][e] : v[2][e];
             // t = sum_eta conj(k_eta S_eta) w_eta
@@ -597,68 +702,80 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
         if (f < F) {
             __syncthreads();
             fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
-            const int64_t pb = (int64_t)f * g.ncell + base;
+            cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
 #pragma unroll
             for (int b = 0; b < N / (RL * P::TPC); ++b)
 #pragma unroll
-                for (int r = 0; r < RL; ++r) w[pb + (int64_t)out_index<P, 1>(lane, b, r) * es] = v[f][b * RL + r];
+                for (int r = 0; r < RL; ++r)
+                    wf[(uint32_t)col + (uint32_t)out_index<P, 1>(lane, b, r) * es32] = v[f][b * RL + r];
         }
     }
 }
 
 // ---------------------------------------------------------- reductions --
-// One block per slot.  CBS: advance the iteration counter, compute the
-// relative update |dx| / |x_k| (skipped while x_k = 0, i.e. the first
-// iteration), raise done on tolerance, cap, non-finite values or three
-// consecutive updates larger than twice the iterate.
-template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_cbs(const Slot<T>* slots, int nparts) {
+// Two levels, one launch: grid = (blocks, slots); block b folds partial pairs
+// [b * kReduceChunk, (b + 1) * kReduceChunk) into chunks[b]; the block that
+// arrives last folds the chunk sums in index order (so the totals do not
+// depend on scheduling) and finalises the slot's control block.
+//   CBS: advance the iteration counter, relative update |dx| / |x_k| (not
+//   tested while x_k = 0, the first iteration), done on tolerance, cap,
+//   non-finite values or three consecutive updates above twice the iterate.
+//   APPLY: |r|^2, |y|^2 and |r| for the refinement kernels.
+template <typename T, bool CBSMODE>
+__global__ void __launch_bounds__(256) k_reduce(const Slot<T>* slots, int nparts) {
     __shared__ double red[16];
-    Ctl* c = slots[blockIdx.x].ctl;
-    if (c->done) return;
-    const double* p = slots[blockIdx.x].partials;
+    __shared__ int last;
+    const Slot<T>& s = slots[blockIdx.y];
+    Ctl* c = s.ctl;
+    if (CBSMODE && c->done) return;
+    const double* p = s.partials;
+    const int b0 = blockIdx.x * kReduceChunk;
+    const int b1 = min(nparts, b0 + kReduceChunk);
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
         a += p[2 * i];
         b += p[2 * i + 1];
     }
     block_sum2(a, b, red);
     if (threadIdx.x == 0) {
-        const int it = c->iter + 1;
-        c->iter = it;
-        const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
-        c->rel_update = rel;
-        c->xnorm2 = b;
-        int done = RUNNING;
-        if (!isfinite(a) || !isfinite(b)) {
-            done = DIVERGED;
-        } else {
-            c->grow = (it >= 3 && rel > 2.0) ? c->grow + 1 : 0;
-            if (c->grow >= 3) done = DIVERGED;
-            else if (b > 0.0 && rel <= c->tol) done = CONVERGED;
-            else if (it >= c->max_iter) done = CAPPED;
-        }
-        c->done = done;
+        s.chunks[2 * blockIdx.x] = a;
+        s.chunks[2 * blockIdx.x + 1] = b;
+        __threadfence();
+        last = atomicAdd(&c->arrive, 1) == (int)gridDim.x - 1;
     }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_apply(const Slot<T>* slots, int nparts) {
-    __shared__ double red[16];
-    Ctl* c = slots[blockIdx.x].ctl;
-    const double* p = slots[blockIdx.x].partials;
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        a += p[2 * i];
-        b += p[2 * i + 1];
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x != 0) return;
+    a = 0.0;
+    b = 0.0;
+    for (int i = 0; i < (int)gridDim.x; ++i) {
+        a += ((volatile double*)s.chunks)[2 * i];
+        b += ((volatile double*)s.chunks)[2 * i + 1];
     }
-    block_sum2(a, b, red);
-    if (threadIdx.x == 0) {
+    c->arrive = 0;
+    if (!CBSMODE) {
         c->res2 = a;
         c->rhs2 = b;
         c->scale = sqrt(a);
         c->res_done += 1;
+        return;
     }
+    const int it = c->iter + 1;
+    c->iter = it;
+    const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+    c->rel_update = rel;
+    c->xnorm2 = b;
+    int done = RUNNING;
+    if (!isfinite(a) || !isfinite(b)) {
+        done = DIVERGED;
+    } else {
+        c->grow = (it >= 3 && rel > 2.0) ? c->grow + 1 : 0;
+        if (c->grow >= 3) done = DIVERGED;
+        else if (b > 0.0 && rel <= c->tol) done = CONVERGED;
+        else if (it >= c->max_iter) done = CAPPED;
+    }
+    c->done = done;
 }
 
 __global__ void k_ctl_reset(Ctl* c, int max_iter, double tol) {
@@ -848,31 +965,38 @@ int plan_tpc(int n, bool wide) {
 
 bool plan_has_wide(int n) { return n == 64 || n == 128 || n == 256; }
 
-// Launch one pass.  kind: 0 contiguous-first, 1 contiguous-last, 2 strided
-// forward, 3 strided inverse, 4 propagator.
+// Launch one pass.  kind: 0 last-axis forward with prologue, 1 last-axis
+// inverse with epilogue, 5 both fused across iterations, 2 strided forward,
+// 3 strided inverse, 4 axis-0 propagator.
 template <typename T, class P>
 static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis,
                               int pcols, hipStream_t st) {
     const int N = P::N;
     const int ldp = pcols + 1;
-    size_t lds = (size_t)N * ldp * sizeof(cx<T>);
+    // tile + twiddles + (propagator) k0 S0 and k0 tables
+    size_t lds = tile_bytes<T>((size_t)N * ldp) + (size_t)N * (2 * sizeof(cx<T>) + sizeof(T));
     if (lds < 64 * sizeof(double)) lds = 64 * sizeof(double);
     const dim3 block(pcols * P::TPC);
     const int F = g.ndim + 1;
     const int last = g.ndim - 1;
-    if (kind == 0 || kind == 1) {
+    if (kind == 0 || kind == 1 || kind == 5) {
         const int64_t tiles = g.ncell / ((int64_t)N * pcols);
         const dim3 grid((unsigned)tiles, F, nslots);
+        const dim3 blk(pcols * P::TPC);
+        const size_t lr = std::max(tile_bytes<T>((size_t)pcols * lds_pitch<ROWS>(N, 0)), (size_t)(64 * sizeof(double))) +
+                          (size_t)N * (sizeof(cx<T>) + sizeof(T));
         if (kind == 0) {
             if (mode == CBS)
-                hipLaunchKernelGGL((k_contig<P, CBS, true, T>), grid, block, lds, st, slots, g, pcols, ldp);
+                hipLaunchKernelGGL((k_lastaxis<P, CBS, FIRST, T>), grid, blk, lr, st, slots, g, pcols);
             else
-                hipLaunchKernelGGL((k_contig<P, APPLY, true, T>), grid, block, lds, st, slots, g, pcols, ldp);
-        } else {
+                hipLaunchKernelGGL((k_lastaxis<P, APPLY, FIRST, T>), grid, blk, lr, st, slots, g, pcols);
+        } else if (kind == 1) {
             if (mode == CBS)
-                hipLaunchKernelGGL((k_contig<P, CBS, false, T>), grid, block, lds, st, slots, g, pcols, ldp);
+                hipLaunchKernelGGL((k_lastaxis<P, CBS, LAST, T>), grid, blk, lr, st, slots, g, pcols);
             else
-                hipLaunchKernelGGL((k_contig<P, APPLY, false, T>), grid, block, lds, st, slots, g, pcols, ldp);
+                hipLaunchKernelGGL((k_lastaxis<P, APPLY, LAST, T>), grid, blk, lr, st, slots, g, pcols);
+        } else {
+            hipLaunchKernelGGL((k_lastaxis<P, CBS, FUSED, T>), grid, blk, lr, st, slots, g, pcols);
         }
     } else {
         // strided along `axis`; columns run along the last axis in groups of pcols
@@ -931,10 +1055,11 @@ template hipError_t launch_pass<double>(int, int, const Slot<double>*, int, cons
 
 template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st) {
+    const dim3 grid((unsigned)((nparts + kReduceChunk - 1) / kReduceChunk), nslots);
     if (cbs_mode)
-        hipLaunchKernelGGL((k_reduce_cbs<T>), dim3(nslots), dim3(256), 0, st, slots, nparts);
+        hipLaunchKernelGGL((k_reduce<T, true>), grid, dim3(256), 0, st, slots, nparts);
     else
-        hipLaunchKernelGGL((k_reduce_apply<T>), dim3(nslots), dim3(256), 0, st, slots, nparts);
+        hipLaunchKernelGGL((k_reduce<T, false>), grid, dim3(256), 0, st, slots, nparts);
     return hipGetLastError();
 }
 template hipError_t launch_reduce<float>(bool, const Slot<float>*, int, int, hipStream_t);

@@ -231,3 +231,91 @@ def gradient(m: Medium, s_p, s_u, p, u, lp, lu, stream=None):
                                  *[_ptr(o) for o in outs], _stream_ptr(stream) if device else None),
             "cbs_gradient")
     return tuple(o.reshape(m.shape) for o in outs)
+
+
+class Batch:
+    """Same-shape slots advanced together (continuous batching).
+
+    Owns a device workspace (torch allocation) sized for ``max_slots`` solves
+    and a HIP stream; every call must come from one thread at a time."""
+
+    def __init__(self, shape, dx_ref, prec="fp32_refined", max_slots=4, stream=None):
+        torch = _torch()
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.ncell = int(np.prod(self.shape))
+        self.prec = prec
+        self.max_slots = int(max_slots)
+        g = L.Grid()
+        g.ndim = self.ndim
+        for d in range(3):
+            g.n[d] = self.shape[d] if d < self.ndim else 1
+        g.dx, g.omega = float(dx_ref), 1.0
+        self.grid = g
+        b = C.c_size_t()
+        L.check(L.lib().cbs_batch_workspace_bytes(C.byref(g), PREC[prec], self.max_slots, C.byref(b)),
+                "cbs_batch_workspace_bytes")
+        self.workspace_bytes = b.value
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        L.check(L.lib().cbs_batch_create(C.byref(g), PREC[prec], self.max_slots,
+                                         C.c_void_p(self.ws.data_ptr()), self.workspace_bytes,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                "cbs_batch_create")
+        self._h = h
+        self.media = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            L.lib().cbs_batch_destroy(h)
+            self._h = None
+
+    def submit(self, m: Medium, s_p, s_u=None, *, tol=1e-5, max_iter=200000, inner_tol=0.0,
+               max_outer=0) -> int:
+        """Start a solve in a free slot; returns the slot index or -1 if full."""
+        device = _is_tensor(s_p)
+        N = m.ncell
+        sp = _dev_c128(s_p.reshape(-1), N) if device else _host_c128(s_p, N)
+        su = None
+        if s_u is not None:
+            su = _dev_c128(s_u.reshape(-1), m.ndim * N) if device else _host_c128(s_u, m.ndim * N)
+        o = _opts(tol, max_iter, self.prec, 0, inner_tol, L.CBS_RHS_PHYSICAL,
+                  L.CBS_PTR_DEVICE if device else L.CBS_PTR_HOST, L.CBS_STOP_UPDATE, max_outer)
+        slot = C.c_int32(-1)
+        st = L.lib().cbs_batch_submit(self._h, m.handle, _ptr(sp), _ptr(su), C.byref(o), C.byref(slot))
+        if st == L.CBS_E_NOMEM:
+            return -1
+        L.check(st, "cbs_batch_submit")
+        self.media[slot.value] = m      # keep the medium alive while its slot runs
+        return slot.value
+
+    def step(self, iterations=32):
+        """Advance every active slot; returns the list of finished slots."""
+        mask = (C.c_uint8 * self.max_slots)()
+        L.check(L.lib().cbs_batch_step(self._h, int(iterations), mask), "cbs_batch_step")
+        return [i for i in range(self.max_slots) if mask[i]]
+
+    def retire(self, slot, want_u=False, device=False):
+        """Copy a finished slot's (p, u) out and free the slot."""
+        torch = _torch()
+        N = self.ncell
+        if device:
+            p = torch.empty(N, dtype=torch.complex128, device="cuda")
+            u = torch.empty(self.ndim * N, dtype=torch.complex128, device="cuda") if want_u else None
+            kind = L.CBS_PTR_DEVICE
+        else:
+            p = np.empty(N, np.complex128)
+            u = np.empty(self.ndim * N, np.complex128) if want_u else None
+            kind = L.CBS_PTR_HOST
+        info = L.SolveInfo()
+        st = L.lib().cbs_batch_retire(self._h, int(slot), _ptr(p), _ptr(u), kind, C.byref(info))
+        L.check(st, "cbs_batch_retire", (L.CBS_OK, L.CBS_NOT_CONVERGED))
+        self.media.pop(int(slot), None)
+        d = info.as_dict()
+        d["converged"] = st == L.CBS_OK
+        p = p.reshape(self.shape)
+        if u is not None:
+            u = u.reshape((self.ndim,) + self.shape)
+        return p, u, d
