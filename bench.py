@@ -41,6 +41,37 @@ PASS_NAMES = ["fwd_axis2_prologue", "fwd_axis1", "axis0_propagator", "inv_axis1"
 PASS_BYTES_F32 = [116, 64, 64, 64, 180]
 
 
+KERNEL_FOR_PASS = {"inv_axis2_update_fwd_axis2": "k_lastaxis", "axis0_propagator": "k_prop",
+                   "fwd_axis1": "k_strided", "inv_axis1": "k_strided"}
+
+
+def committed_traffic(pass_name, plan):
+    """Calibrated HBM bytes per launch of this pass from the committed rocprofv3
+    counter summary, or None if the kernels changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "shell256_traffic.txt")
+    src = os.path.join(ROOT, "paper_2507_16087_amd", "csrc", "cbs_kernels.hip")
+    if not os.path.exists(prof):
+        return None
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    text = open(prof).read()
+    if f"sha256[:16]: {cur}" not in text:
+        return None
+    want = KERNEL_FOR_PASS.get(pass_name)
+    tpl = f"Plan<{plan['n']}, " if plan else ""
+    for line in text.splitlines():
+        if line.startswith("#") or not line.startswith(want or "?"):
+            continue
+        parts = line.split()
+        if "float>" in line and tpl in line:
+            if pass_name == "inv_axis1" and ", 1, float>" not in line:
+                continue
+            if pass_name == "fwd_axis1" and ", -1, float>" not in line:
+                continue
+            return float(parts[-2])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -61,6 +92,36 @@ def oracle_baseline(prob, iters: int):
                        f"{'x'.join(map(str, prob.shape))} workload ({dt:.1f} s)")
 
 
+def serving_leg(n_requests: int, log_fn):
+    """Mixed-size request stream (64^3..192^3 random media, 0.25-1 MHz, refined
+    FP32 to 1e-5) through the continuous-batching server.  A burst of the
+    first requests measures capacity; the stream then arrives as a Poisson
+    process at 0.8 of that capacity."""
+    from paper_2507_16087_amd import workloads as W
+    from paper_2507_16087_amd.serve import Server
+    probe = W.request_stream(count=min(16, n_requests), rate_hz=1e6, seed=4242)
+    t0 = time.perf_counter()
+    cap = Server(tol=1e-5, slots_per_pool=4, step_iters=32).run(probe)
+    log_fn(f"serving capacity probe: {len(probe)} solves in {cap['wall_s']:.2f} s "
+           f"({cap['solves_per_s']:.2f}/s)")
+    rate = 0.8 * cap["solves_per_s"]
+    reqs = W.request_stream(count=n_requests, rate_hz=rate, seed=4242)
+    out = Server(tol=1e-5, slots_per_pool=4, step_iters=32).run(reqs)
+    log_fn(f"serving: {n_requests} requests at {rate:.2f}/s: p50 {out['p50_ms']:.0f} ms, "
+           f"p99 {out['p99_ms']:.0f} ms, {out['solves_per_s']:.2f} solves/s, "
+           f"{time.perf_counter() - t0:.1f} s total")
+    sizes = {}
+    for r in out["results"]:
+        sizes.setdefault(r.shape[0], []).append(r.latency * 1e3)
+    return {"requests": n_requests, "arrival_rate_hz": round(rate, 3),
+            "capacity_probe_solves_per_s": round(cap["solves_per_s"], 3),
+            "p50_ms": round(out["p50_ms"], 1), "p99_ms": round(out["p99_ms"], 1),
+            "solves_per_s": round(out["solves_per_s"], 3), "converged": out["converged"],
+            "max_concurrency": out["max_concurrency"],
+            "p50_ms_by_size": {str(k): round(float(np.median(v)), 1) for k, v in sorted(sizes.items())},
+            "precision": "fp32 inner, fp64 refinement, tol 1e-5"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +134,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="cap on inner iterations per solve (short profiling runs)")
     args = ap.parse_args()
@@ -175,8 +238,10 @@ def main():
         k = best
         avg = ms[k] / cnt[k]
         ach = PASS_BYTES_F32[k] * prob.ncell / (avg * 1e-3) / 1e9
+        plan = plans["fp32"][k] if k < len(plans["fp32"]) else None
+        traffic = committed_traffic(PASS_NAMES[k], plan)
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                           "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                            "kernel": PASS_NAMES[k],
                            "bytes_per_launch": PASS_BYTES_F32[k] * prob.ncell,
                            "avg_launch_ms": round(avg, 5)}
@@ -196,6 +261,14 @@ def main():
         out["gcell_iter_s_fp64"] = round(prob.ncell * i64["iterations"] / t64 / 1e9, 4)
         out["speedup_refined_vs_fp64"] = round(t64 / (dt / args.steps), 3)
         del ws64
+
+    if not args.no_serve:
+        del ws32
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args.serve_requests, log)
+        out["p50_ms"] = out["serving"]["p50_ms"]
+        out["p99_ms"] = out["serving"]["p99_ms"]
+        ws32 = None
 
     if not args.no_cpu:
         del ws32

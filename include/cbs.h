@@ -110,7 +110,11 @@ typedef struct {
     int32_t rhs_kind;        /* CBS_RHS_PHYSICAL or CBS_RHS_EQUATION                */
     int32_t ptr_kind;        /* pointer kind of sources and outputs                 */
     int32_t stop_rule;       /* CBS_STOP_UPDATE or CBS_STOP_RESIDUAL (FP64 only)    */
-    int32_t max_outer;       /* refined: cap on outer steps (0 -> 50)               */
+    int32_t max_outer;       /* refined: cap on outer steps (0 -> 10000)            */
+    int32_t max_inner;       /* refined: cap on iterations per inner run (0 -> 256);
+                                a stationary iteration restarted on its residual
+                                loses nothing, so short inner runs only add FP64
+                                residual checks and bound the overshoot           */
 } cbs_solve_opts;
 
 typedef struct {
@@ -229,7 +233,10 @@ cbs_status cbs_batch_submit(cbs_batch b, cbs_medium m, const void *s_p, const vo
                             const cbs_solve_opts *opts, int32_t *slot);
 
 /* Advance every active slot by up to `iterations` CBS iterations (refined
- * slots also run their outer steps), then poll.  done_mask receives one
+ * slots also run their outer steps), then poll.  The iterations are captured
+ * once per (active slots, starting slots, iterations) as a HIP graph and
+ * replayed (CBS_BATCH_GRAPHS=0 in the environment launches them directly);
+ * the stream given to cbs_batch_create must therefore not be capturing.  done_mask receives one
  * byte per slot: 1 when that slot has finished (converged, capped or
  * diverged) and awaits retirement. */
 cbs_status cbs_batch_step(cbs_batch b, int32_t iterations, uint8_t *done_mask);

@@ -49,7 +49,8 @@ class Grid(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("prec", C.c_int32),
                 ("check_every", C.c_int32), ("inner_tol", C.c_double), ("rhs_kind", C.c_int32),
-                ("ptr_kind", C.c_int32), ("stop_rule", C.c_int32), ("max_outer", C.c_int32)]
+                ("ptr_kind", C.c_int32), ("stop_rule", C.c_int32), ("max_outer", C.c_int32),
+                ("max_inner", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -1047,7 +1047,8 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
         Slot<float> h32 = make_slot<float>(m, d32, w32, y32, ctl32, part32, adjoint, at<double>(ws, L.off_chunk32));
         HIPOK(hipMemcpyAsync(dslot32, &h32, sizeof(h32), hipMemcpyHostToDevice, st));
         const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
-        const int max_outer = o->max_outer > 0 ? o->max_outer : 50;
+        const int max_outer = o->max_outer > 0 ? o->max_outer : 10000;
+        const int64_t max_inner = o->max_inner > 0 ? o->max_inner : 256;
         // x64 = 0 so the first residual is y: evaluate it with the APPLY passes
         int64_t total = 0;
         for (int outer = 0;; ++outer) {
@@ -1070,7 +1071,7 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
             }
             HIPOK(launch_convert(w64, y32, nf, ctl64, st));
             HIPOK(launch_zero<float>(d32, nf, st));
-            const int64_t cap = o->max_iter - total;
+            const int64_t cap = std::min<int64_t>(o->max_iter - total, max_inner);
             HIPOK(launch_ctl_reset(ctl32, (int)cap, inner_tol, st));
             Ctl ic{};
             int64_t launched = 0;
@@ -1307,6 +1308,11 @@ struct cbs_batch_s {
     Slot<double>* hc64 = nullptr;   // pinned staging of the same
     Slot<float>* hc32 = nullptr;
     Ctl* hctl = nullptr;            // pinned: one control block per slot
+    // instantiated graphs of `iterations` CBS iterations, keyed by
+    // (slots, starting slots, iterations); the descriptors they read are
+    // refreshed in place before each launch
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    bool use_graphs = true;
     char* region(int i) const { return ws + header + (size_t)i * slot_bytes; }
 };
 
@@ -1344,7 +1350,7 @@ cbs_status batch_residual_phase(cbs_batch_s* b) {
         const Ctl& c = b->hctl[i];
         sl.res_evals++;
         sl.rel_res = c.rhs2 > 0 ? std::sqrt(c.res2 / c.rhs2) : 0.0;
-        const int max_outer = sl.o.max_outer > 0 ? sl.o.max_outer : 50;
+        const int max_outer = sl.o.max_outer > 0 ? sl.o.max_outer : 10000;
         if (!std::isfinite(sl.rel_res)) {
             sl.status = CBS_E_DIVERGED;
             sl.phase = PH_DONE;
@@ -1358,7 +1364,9 @@ cbs_status batch_residual_phase(cbs_batch_s* b) {
             const double inner_tol = sl.o.inner_tol > 0 ? sl.o.inner_tol : 1e-3;
             HIPOK(launch_convert(sl.h64.w, const_cast<cx<float>*>(sl.h32.y), nf, sl.h64.ctl, b->st));
             HIPOK(launch_zero<float>(sl.h32.x, nf, b->st));
-            HIPOK(launch_ctl_reset(sl.h32.ctl, (int)(sl.o.max_iter - sl.iters), inner_tol, b->st));
+            const int64_t max_inner = sl.o.max_inner > 0 ? sl.o.max_inner : 256;
+            HIPOK(launch_ctl_reset(sl.h32.ctl, (int)std::min<int64_t>(sl.o.max_iter - sl.iters, max_inner),
+                                   inner_tol, b->st));
             sl.phase = PH_CBS;
             sl.start = true;
         }
@@ -1384,8 +1392,31 @@ cbs_status batch_cbs_phase(cbs_batch_s* b, int iterations, Slot<T>* dc, Slot<T>*
     for (int k = 0; k < ns; ++k) hc[b->maxs + k] = desc(starts[k]);
     HIPOK(hipMemcpyAsync(dc, hc, sizeof(Slot<T>) * n, hipMemcpyHostToDevice, b->st));
     if (ns) HIPOK(hipMemcpyAsync(dc + b->maxs, hc + b->maxs, sizeof(Slot<T>) * ns, hipMemcpyHostToDevice, b->st));
-    for (int it = 0; it < iterations; ++it)
-        HIPOK(run_passes_set<T>(b->g, nullptr, ps, MODE_CBS, dc, n, dc + b->maxs, it == 0 ? ns : 0, b->st));
+    if (b->use_graphs) {
+        const auto key = std::make_tuple(n, ns, iterations);
+        auto itg = b->graphs.find(key);
+        if (itg == b->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            HIPOK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipSuccess;
+            for (int it = 0; it < iterations && ce == hipSuccess; ++it)
+                ce = run_passes_set<T>(b->g, nullptr, ps, MODE_CBS, dc, n, dc + b->maxs, it == 0 ? ns : 0, b->st);
+            const hipError_t ee = hipStreamEndCapture(b->st, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return CBS_E_DEVICE;
+            }
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return CBS_E_DEVICE;
+            itg = b->graphs.emplace(key, exec).first;
+        }
+        HIPOK(hipGraphLaunch(itg->second, b->st));
+    } else {
+        for (int it = 0; it < iterations; ++it)
+            HIPOK(run_passes_set<T>(b->g, nullptr, ps, MODE_CBS, dc, n, dc + b->maxs, it == 0 ? ns : 0, b->st));
+    }
     for (int i : idx) {
         b->s[i].start = false;
         HIPOK(hipMemcpyAsync(&b->hctl[i], desc(i).ctl, sizeof(Ctl), hipMemcpyDeviceToHost, b->st));
@@ -1449,6 +1480,10 @@ cbs_status cbs_batch_create(const cbs_grid* grid, int32_t prec, int32_t max_slot
     b->slot_bytes = b->L.total;
     b->header = batch_header(max_slots);
     b->s.resize(max_slots);
+    {
+        const char* e = std::getenv("CBS_BATCH_GRAPHS");
+        b->use_graphs = !(e && e[0] == '0');
+    }
     b->dc64 = reinterpret_cast<Slot<double>*>(b->ws);
     b->dc32 = reinterpret_cast<Slot<float>*>(b->ws + align_up(2 * (size_t)max_slots * sizeof(Slot<double>)));
     if (hipHostMalloc((void**)&b->hc64, 2 * sizeof(Slot<double>) * max_slots) != hipSuccess ||
@@ -1464,6 +1499,7 @@ cbs_status cbs_batch_create(const cbs_grid* grid, int32_t prec, int32_t max_slot
 cbs_status cbs_batch_destroy(cbs_batch b) {
     if (!b) return CBS_E_INVALID;
     (void)hipStreamSynchronize(b->st);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     if (b->hc64) (void)hipHostFree(b->hc64);
     if (b->hc32) (void)hipHostFree(b->hc32);
     if (b->hctl) (void)hipHostFree(b->hctl);

@@ -537,6 +537,18 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
         for (int r = 0; r < RLF; ++r) w[pl + out_index<P, -1>(lane, b, r)] = v[b * RLF + r];
 }
 
+// XCD-aware tile order.  Work-groups are dispatched round-robin over the 8
+// XCDs, each with its own L2.  When a tile's row segments are narrower than a
+// 128-byte line, G neighbouring tiles share every line; this map sends those
+// G tiles to the same XCD one after another, so each line is fetched from HBM
+// once.  Identity when G = 1 or the grid does not split evenly.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int G) {
+    constexpr unsigned X = 8;
+    if (G <= 1 || nb % (X * (unsigned)G)) return b;
+    const unsigned x = b % X, s = b / X;
+    return ((s / (unsigned)G) * X + x) * (unsigned)G + (s % (unsigned)G);
+}
+
 // ------------------------------------------- pass B / D: strided axis --
 // FFT along axis `axis` (< ndim - 1) of the w buffer, in place.  Tile = P
 // adjacent columns along the last axis; the first stage loads straight from
@@ -544,15 +556,16 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
 template <class P, int DIR, typename T>
 __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slots, Geom g, int axis,
                                                  int pcols, int ldp, int64_t es, int64_t ostride,
-                                                 int nlast_tiles, int skip_done) {
+                                                 int nlast_tiles, int skip_done, int xg) {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
     if (skip_done && s.ctl->done) return;
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
-    cx<T>* __restrict__ w = s.w + (int64_t)blockIdx.y * g.ncell + (int64_t)(blockIdx.x / nlast_tiles) * ostride +
-                            (int64_t)(blockIdx.x % nlast_tiles) * pcols;
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
+    cx<T>* __restrict__ w = s.w + (int64_t)blockIdx.y * g.ncell + (int64_t)(tile / nlast_tiles) * ostride +
+                            (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
     cx<T> v[P::E];
     constexpr int NB0 = P::N / (Seq<P, DIR>::r(0) * P::TPC);
@@ -582,7 +595,7 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 // derivative block of L (negated for the adjoint).  1/prod(n) is folded in.
 template <class P, int MODE, typename T>
 __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols,
-                                              int ldp, int64_t es, int64_t ostride, int nlast_tiles) {
+                                              int ldp, int64_t es, int64_t ostride, int nlast_tiles, int xg) {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
@@ -591,9 +604,10 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     const int D = g.ndim, F = D + 1;
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
-    const int io = blockIdx.x / nlast_tiles;                       // index along the middle axis (3-D)
-    const int il = (blockIdx.x % nlast_tiles) * pcols + col;       // index along the last axis
-    cx<T>* __restrict__ wt = s.w + (int64_t)io * ostride + (int64_t)(blockIdx.x % nlast_tiles) * pcols;
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
+    const int io = tile / nlast_tiles;                              // index along the middle axis (3-D)
+    const int il = (tile % nlast_tiles) * pcols + col;              // index along the last axis
+    cx<T>* __restrict__ wt = s.w + (int64_t)io * ostride + (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
     // LDS: tile | twiddles (N) | k0 S0 (N) | k0 (N)
     cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tile_bytes<T>((size_t)N * ldp));
@@ -1015,23 +1029,26 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
             nother = g.n[other];
         }
         const unsigned tiles = (unsigned)(nlast_tiles * nother);
+        // tiles sharing each 128-byte line (adjacent along the last axis)
+        int xg = (int)(128 / ((size_t)pcols * sizeof(cx<T>)));
+        if (xg < 1 || nlast_tiles % xg) xg = 1;
         if (kind == 4) {
             const dim3 grid(tiles, 1, nslots);
             if (mode == CBS)
                 hipLaunchKernelGGL((k_prop<P, CBS, T>), grid, block, lds, st, slots, g, pcols, ldp, es, ostride,
-                                   nlast_tiles);
+                                   nlast_tiles, xg);
             else
                 hipLaunchKernelGGL((k_prop<P, APPLY, T>), grid, block, lds, st, slots, g, pcols, ldp, es, ostride,
-                                   nlast_tiles);
+                                   nlast_tiles, xg);
         } else {
             const dim3 grid(tiles, F, nslots);
             const int skip = mode == CBS ? 1 : 0;
             if (kind == 2)
                 hipLaunchKernelGGL((k_strided<P, -1, T>), grid, block, lds, st, slots, g, axis, pcols, ldp, es,
-                                   ostride, nlast_tiles, skip);
+                                   ostride, nlast_tiles, skip, xg);
             else
                 hipLaunchKernelGGL((k_strided<P, 1, T>), grid, block, lds, st, slots, g, axis, pcols, ldp, es,
-                                   ostride, nlast_tiles, skip);
+                                   ostride, nlast_tiles, skip, xg);
         }
     }
     return hipGetLastError();

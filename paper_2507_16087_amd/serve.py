@@ -1,0 +1,216 @@
+"""Continuous-batching request loop for the iterative Born solver.
+
+Requests (a grid, a frequency, a medium and a source) arrive over time.  Each
+is admitted when its HBM footprint fits the budget and a slot of its grid
+shape is free; admitted requests are planned (medium setup, on a host thread
+pool) and submitted as slots of a per-shape :class:`solver.Batch`.  Every
+shape pool runs on its own HIP stream and host thread, advancing all of its
+active slots together (one kernel launch per pass covers every slot) a fixed
+number of iterations per step, retiring finished slots and taking new ones
+between steps.  Pools of different shapes therefore overlap on the device,
+and a request that arrives while others run joins the next step of its pool.
+
+A slot's result depends only on its own request: same kernels and plans as
+a single solve, no data shared between slots, deterministic reductions.
+
+Latency is measured from a request's arrival to its result being on the host.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import dataclasses
+import queue
+import threading
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import solver
+
+MEDIUM_BYTES_PER_CELL = 8 * 3 + 16 + 4 * 3 + 8 + 8 * 3   # rhobar, q (FP64, FP32), c, rho, alpha
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    shape: tuple
+    arrival: float
+    admitted: float = 0.0
+    submitted: float = 0.0
+    done: float = 0.0
+    iterations: int = 0
+    outer: int = 0
+    rel_residual: float = -1.0
+    converged: bool = False
+    p: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Pool:
+    def __init__(self, server: "Server", shape, dx):
+        self.server = server
+        self.shape = shape
+        self.batch = solver.Batch(shape, dx, prec=server.prec, max_slots=server.slots_per_pool)
+        self.inbox: "queue.Queue" = queue.Queue()
+        self.reserved = 0          # slots promised to admitted requests (planning or running)
+        self.slot_rid: Dict[int, int] = {}
+        self.thread = threading.Thread(target=self._loop, daemon=True)
+        self.stop = False
+        self.thread.start()
+
+    def _loop(self):
+        import torch
+        torch.cuda.set_device(0)
+        while True:
+            try:
+                item = self.inbox.get(timeout=0.002 if self.slot_rid else 0.05)
+            except queue.Empty:
+                item = None
+            while item is not None:
+                rid, medium, sp = item
+                slot = self.batch.submit(medium, sp, tol=self.server.tol,
+                                         inner_tol=self.server.inner_tol)
+                assert slot >= 0, "admission promised a free slot"
+                self.slot_rid[slot] = rid
+                self.server._mark(rid, "submitted")
+                try:
+                    item = self.inbox.get_nowait()
+                except queue.Empty:
+                    item = None
+            if not self.slot_rid:
+                if self.stop:
+                    return
+                continue
+            for slot in self.batch.step(self.server.step_iters):
+                p, _, info = self.batch.retire(slot)
+                rid = self.slot_rid.pop(slot)
+                self.server._finish(rid, self, p, info)
+
+
+class Server:
+    """Serve a stream of solve requests with continuous batching."""
+
+    def __init__(self, prec="fp32_refined", tol=1e-5, inner_tol=0.0, slots_per_pool=4,
+                 step_iters=32, hbm_budget: Optional[int] = None, plan_workers=4,
+                 keep_fields=False):
+        import torch
+        self.prec, self.tol, self.inner_tol = prec, tol, inner_tol
+        self.slots_per_pool, self.step_iters = slots_per_pool, step_iters
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(0.8 * free)
+        self.budget = hbm_budget
+        self.used = 0
+        self.keep_fields = keep_fields
+        self.pools: Dict[tuple, _Pool] = {}
+        self.results: Dict[int, Result] = {}
+        self.lock = threading.Lock()
+        self.cv = threading.Condition(self.lock)
+        self.planner = cf.ThreadPoolExecutor(max_workers=plan_workers)
+        self.timeline: List[tuple] = []   # (time, active solves)
+        self.active = 0
+
+    # -- accounting -------------------------------------------------------
+    def _mark(self, rid, what):
+        with self.lock:
+            setattr(self.results[rid], what, time.perf_counter())
+
+    def _finish(self, rid, pool, p, info):
+        with self.cv:
+            r = self.results[rid]
+            r.done = time.perf_counter()
+            r.iterations, r.outer = info["iterations"], info["outer"]
+            r.rel_residual, r.converged = info["rel_residual"], info["converged"]
+            if self.keep_fields:
+                r.p = p
+            pool.reserved -= 1
+            self.used -= self._medium_bytes(pool.shape)
+            self.active -= 1
+            self.timeline.append((r.done, self.active))
+            self.cv.notify_all()
+
+    @staticmethod
+    def _medium_bytes(shape):
+        return int(np.prod(shape)) * MEDIUM_BYTES_PER_CELL
+
+    def footprint(self, shape, new_pool: bool) -> int:
+        """HBM bytes admitting one request of this shape needs now."""
+        need = self._medium_bytes(shape)
+        if new_pool:
+            b = solver.L.lib()
+            import ctypes as C
+            g = solver.L.Grid()
+            g.ndim = len(shape)
+            for d in range(3):
+                g.n[d] = shape[d] if d < len(shape) else 1
+            g.dx, g.omega = 1.0, 1.0
+            nb = C.c_size_t()
+            solver.L.check(b.cbs_batch_workspace_bytes(C.byref(g), solver.PREC[self.prec],
+                                                       self.slots_per_pool, C.byref(nb)),
+                           "cbs_batch_workspace_bytes")
+            need += nb.value
+        return need
+
+    # -- admission --------------------------------------------------------
+    def _try_admit(self, req) -> bool:
+        pr = req.problem
+        shape = pr.shape
+        with self.lock:
+            pool = self.pools.get(shape)
+            if pool is not None and pool.reserved >= self.slots_per_pool:
+                return False
+            need = self.footprint(shape, pool is None)
+            if self.used + need > self.budget:
+                return False
+            self.used += need
+            if pool is None:
+                pool = _Pool(self, shape, pr.dx)
+                self.pools[shape] = pool
+            pool.reserved += 1
+            self.active += 1
+            self.timeline.append((time.perf_counter(), self.active))
+            self.results[req.rid].admitted = time.perf_counter()
+
+        def plan():
+            m = solver.Medium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
+            pool.inbox.put((req.rid, m, pr.dense_source().ravel()))
+
+        self.planner.submit(plan)
+        return True
+
+    def run(self, requests, time_scale: float = 1.0) -> dict:
+        """Replay `requests` (arrival_s relative to start, divided by
+        time_scale) and return per-request results and latency statistics."""
+        reqs = sorted(requests, key=lambda r: r.arrival_s)
+        t0 = time.perf_counter()
+        pending: List = []
+        i = 0
+        for r in reqs:
+            self.results[r.rid] = Result(r.rid, r.problem.shape, t0 + r.arrival_s / time_scale)
+        while True:
+            now = time.perf_counter()
+            while i < len(reqs) and t0 + reqs[i].arrival_s / time_scale <= now:
+                pending.append(reqs[i])
+                i += 1
+            while pending and self._try_admit(pending[0]):
+                pending.pop(0)
+            with self.cv:
+                if i == len(reqs) and not pending and all(r.done > 0 for r in self.results.values()):
+                    break
+                self.cv.wait(timeout=0.002)
+        for p in self.pools.values():
+            p.stop = True
+        for p in self.pools.values():
+            p.thread.join()
+        self.planner.shutdown(wait=True)
+        res = [self.results[r.rid] for r in reqs]
+        lat = np.array([r.latency for r in res]) * 1e3
+        span = max(r.done for r in res) - t0
+        return dict(results=res, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), solves_per_s=len(res) / span,
+                    wall_s=span, max_concurrency=max((a for _, a in self.timeline), default=0),
+                    converged=sum(r.converged for r in res))

@@ -129,8 +129,10 @@ class Medium:
         return torch.empty(self.workspace_bytes(prec), dtype=torch.uint8, device="cuda")
 
 
-def _opts(tol, max_iter, prec, check_every, inner_tol, rhs_kind, ptr_kind, stop_rule, max_outer):
+def _opts(tol, max_iter, prec, check_every, inner_tol, rhs_kind, ptr_kind, stop_rule, max_outer,
+          max_inner=0):
     o = L.SolveOpts()
+    o.max_inner = int(max_inner)
     o.tol, o.max_iter, o.prec = float(tol), int(max_iter), PREC[prec]
     o.check_every, o.inner_tol = int(check_every), float(inner_tol)
     o.rhs_kind, o.ptr_kind, o.stop_rule, o.max_outer = int(rhs_kind), int(ptr_kind), int(stop_rule), int(max_outer)
@@ -139,7 +141,7 @@ def _opts(tol, max_iter, prec, check_every, inner_tol, rhs_kind, ptr_kind, stop_
 
 def solve(m: Medium, s_p, s_u=None, *, tol=1e-8, max_iter=100000, prec="fp64", check_every=32,
           inner_tol=0.0, equation_rhs=False, stop_rule=L.CBS_STOP_UPDATE, max_outer=0,
-          adjoint=False, want_u=True, workspace=None, stream=None, raise_on_cap=False):
+          max_inner=0, adjoint=False, want_u=True, workspace=None, stream=None, raise_on_cap=False):
     """Solve A xi = s_hat (or A^H xi = s_hat).  Returns (p, u, info).
 
     numpy inputs give numpy outputs (host pointers); CUDA tensors give CUDA
@@ -161,7 +163,8 @@ def solve(m: Medium, s_p, s_u=None, *, tol=1e-8, max_iter=100000, prec="fp64", c
         kind = L.CBS_PTR_HOST
     ws = workspace if workspace is not None else m.workspace(prec)
     o = _opts(tol, max_iter, prec, check_every, inner_tol,
-              L.CBS_RHS_EQUATION if equation_rhs else L.CBS_RHS_PHYSICAL, kind, stop_rule, max_outer)
+              L.CBS_RHS_EQUATION if equation_rhs else L.CBS_RHS_PHYSICAL, kind, stop_rule, max_outer,
+              max_inner)
     info = L.SolveInfo()
     fn = L.lib().cbs_solve_adjoint if adjoint else L.lib().cbs_solve
     st = fn(m.handle, _ptr(sp), _ptr(su), C.byref(o), _ptr(p), _ptr(u), C.c_void_p(ws.data_ptr()),
@@ -273,7 +276,7 @@ class Batch:
             self._h = None
 
     def submit(self, m: Medium, s_p, s_u=None, *, tol=1e-5, max_iter=200000, inner_tol=0.0,
-               max_outer=0) -> int:
+               max_outer=0, max_inner=0) -> int:
         """Start a solve in a free slot; returns the slot index or -1 if full."""
         device = _is_tensor(s_p)
         N = m.ncell
@@ -282,7 +285,8 @@ class Batch:
         if s_u is not None:
             su = _dev_c128(s_u.reshape(-1), m.ndim * N) if device else _host_c128(s_u, m.ndim * N)
         o = _opts(tol, max_iter, self.prec, 0, inner_tol, L.CBS_RHS_PHYSICAL,
-                  L.CBS_PTR_DEVICE if device else L.CBS_PTR_HOST, L.CBS_STOP_UPDATE, max_outer)
+                  L.CBS_PTR_DEVICE if device else L.CBS_PTR_HOST, L.CBS_STOP_UPDATE, max_outer,
+                  max_inner)
         slot = C.c_int32(-1)
         st = L.lib().cbs_batch_submit(self._h, m.handle, _ptr(sp), _ptr(su), C.byref(o), C.byref(slot))
         if st == L.CBS_E_NOMEM:

@@ -233,14 +233,16 @@ class Inversion:
 
 
 def inversion(n: int = 128, seed: int = 2507, shots_yz=(2, 4),
-              receivers_yz=(16, 8)) -> Inversion:
-    """8 single-cell shots at x index ~n*20/128, 128 receivers at ~n*107/128,
-    and a true medium with a smooth bump: c*(1+0.03 b), rho*(1-0.03 b)."""
+              receivers_yz=(16, 8), pml: int = PML_CELLS) -> Inversion:
+    """8 single-cell shots at x index ~n*20/128, 128 receivers at ~n*107/128
+    (kept two cells clear of the absorbing layer), and a true medium with a
+    smooth bump: c*(1+0.03 b), rho*(1-0.03 b)."""
     base = random3d(n, 1e6, seed)
+    base.pml_cells = pml
     shape = base.shape
-    lo, hi = PML_CELLS, n - PML_CELLS
-    xs = int(round(20 * n / 128))
-    xr = int(round(107 * n / 128))
+    lo, hi = pml, n - pml
+    xs = max(pml + 2, int(round(20 * n / 128)))
+    xr = min(n - pml - 3, int(round(107 * n / 128)))
     shots = []
     for jy in lattice(lo, hi, shots_yz[0]):
         for jz in lattice(lo, hi, shots_yz[1]):
