@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--max-iter", type=int, default=200000,
@@ -199,12 +199,7 @@ def main():
     total_pass_ms = sum(ms[k] for k in range(6))
     fp64_res = {k: round(ms[12 + k] / cnt[12 + k], 5) for k in range(6) if cnt[12 + k]}
 
-    plans = {}
-    for prec_name, prec in (("fp32", _lib.CBS_FP32_REFINED), ("fp64", _lib.CBS_FP64)):
-        cfg = (C.c_int32 * 20)()
-        L.cbs_pass_config(m.handle, prec, cfg)
-        plans[prec_name] = [dict(kind=cfg[4 * i], n=cfg[4 * i + 1], cols=cfg[4 * i + 2], wide=cfg[4 * i + 3])
-                            for i in range(5) if cfg[4 * i] >= 0]
+    plans = {"fp32": m.pass_config("fp32_refined"), "fp64": m.pass_config("fp64")}
     value = prob.ncell * iters / dt / 1e9
     out = {
         "metric": "Gcell-iter/s + time-to-1e-5 at 256^3, FP32-refined vs FP64 plain; p50/p99 ms",

@@ -98,6 +98,10 @@ typedef struct {
     double nu;               /* step of eq. BornAlt, 0 < nu <= 1 (0 -> 0.9)         */
     int32_t shift_rule;      /* 0: centre of the minimum enclosing circle of each
                                 diagonal's values; 1: component-wise median          */
+    int32_t collocated;      /* 0: staggered velocities (App. B.1, default);
+                                1: collocated grid (App. B first matrix): every
+                                field at the cell centres, rho and gamma unshifted,
+                                derivative symbol i k with the Nyquist bin zeroed    */
 } cbs_grid;
 
 typedef struct {
@@ -196,10 +200,13 @@ cbs_status cbs_gradient(cbs_medium m, const void *s_p, const void *s_u, const vo
 cbs_status cbs_pass_timing(cbs_medium m, int32_t enable);
 
 /* Pass plans in use for precision prec (after the first solve tunes them):
- * out[4 i + 0..3] = kind, axis length, columns per work-group, wide-plan flag
- * of pass i (kind -1 = unused).  The first solve of each (shape, precision)
+ * out[4 i + 0..3] = kind, axis length, columns per work-group, flags of pass i
+ * (kind -1 = unused; flag bit 0 = wide radix split, bit 1 = fields share each
+ * LDS exchange).  The first solve of each (shape, precision)
  * in a process times the candidate plans on its workspace and keeps the
- * fastest (set CBS_AUTOTUNE=0 in the environment to keep the defaults). */
+ * fastest (set CBS_AUTOTUNE=0 in the environment to keep the defaults;
+ * CBS_PROP_VARIANT=0 or 1 pins the propagator's flag bit 1, tuned or not).
+ * Configurations needing more than 160 KiB of LDS are never launched. */
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
 
 /* Totals so far: ms[g * 6 + k] and launches[g * 6 + k] for group g (0 FP32

@@ -35,6 +35,11 @@
  * over (L + 1/2); periodic wrap of the density average; scale floor
  * lam >= 1e-3 |a|; stopping test skipped at the first iteration.
  *
+ * Collocated variant (App. B, first matrix): every field at the cell centres,
+ * density and absorbing rate unshifted, derivative symbol i k with the
+ * Nyquist bin of each odd derivative set to zero, (L+I)^{-1} the collocated
+ * 3-D matrix (and its 2-D / 1-D restriction).
+ *
  * Complex arrays are interleaved (re, im) doubles; fields are stored as
  * [F][cells] with F = ndim + 1 (u_0..u_{ndim-1}, p), C-ordered cells, last
  * axis contiguous.
@@ -212,6 +217,7 @@ typedef struct {
     int64_t ncell;
     double dx, omega, gmax, beta, nu;
     int pml, shift_rule;
+    int colloc;       /* 1: collocated grid variant                           */
     double *rho, *c, *alpha;
     cplx *q;          /* 1/(rho c_cx^2) per cell                               */
     double *rhobar;   /* [ndim][ncell] staggered density                       */
@@ -223,6 +229,7 @@ typedef struct {
     double lam1, lam2;
     double *kv[3];    /* wavenumbers per axis, FFT order                       */
     cplx *sh[3];      /* half-cell shift factors exp(i k dx/2) per axis        */
+    double *kd[3];    /* collocated derivative wavenumbers (Nyquist bin 0)     */
 } orc_medium;
 
 /* periodic distance of position t from the interior [L, n-1-L], over L+1/2 */
@@ -258,14 +265,15 @@ void orc_destroy(void *h)
     if (!m) return;
     free(m->rho); free(m->c); free(m->alpha); free(m->q); free(m->rhobar);
     free(m->gam); free(m->gams); free(m->Du); free(m->Dp);
-    for (int d = 0; d < 3; ++d) { free(m->kv[d]); free(m->sh[d]); }
+    for (int d = 0; d < 3; ++d) { free(m->kv[d]); free(m->sh[d]); free(m->kd[d]); }
     free(m);
 }
 
-/* Returns 0 on success, -1 on invalid input. */
-int orc_create(int ndim, const int64_t *n, double dx, double omega, int pml,
-               double gmax, double beta, double nu, int shift_rule,
-               const double *c, const double *rho, const double *alpha, void **out)
+/* Returns 0 on success, -1 on invalid input.  colloc selects the collocated
+ * variant. */
+int orc_create2(int ndim, const int64_t *n, double dx, double omega, int pml,
+                double gmax, double beta, double nu, int shift_rule, int colloc,
+                const double *c, const double *rho, const double *alpha, void **out)
 {
     *out = NULL;
     if (ndim < 1 || ndim > 3 || !(dx > 0) || !(omega > 0)) return -1;
@@ -281,7 +289,7 @@ int orc_create(int ndim, const int64_t *n, double dx, double omega, int pml,
     }
     m->dx = dx; m->omega = omega; m->pml = pml;
     m->gmax = gmax > 0 ? gmax : omega;
-    m->beta = beta; m->nu = nu; m->shift_rule = shift_rule;
+    m->beta = beta; m->nu = nu; m->shift_rule = shift_rule; m->colloc = colloc;
     int64_t N = m->ncell;
     for (int64_t i = 0; i < N; ++i)
         if (!(c[i] > 0) || !(rho[i] > 0) || !(alpha[i] >= 0) || !isfinite(c[i]) ||
@@ -313,7 +321,7 @@ int orc_create(int ndim, const int64_t *n, double dx, double omega, int pml,
         for (int e = 0; e < ndim; ++e) {
             double gs = 0.0;
             for (int d = 0; d < ndim; ++d) {
-                double t = (double)ix[d] + (d == e ? 0.5 : 0.0);
+                double t = (double)ix[d] + ((d == e && !colloc) ? 0.5 : 0.0);
                 double r = layer_r(t, (int)m->n[d], pml);
                 gs += r * r;
             }
@@ -323,7 +331,8 @@ int orc_create(int ndim, const int64_t *n, double dx, double omega, int pml,
     /* staggered density: average of rho at x and x + dx e_eta (periodic) */
     for (int e = 0; e < ndim; ++e)
         for (int64_t i = 0; i < N; ++i)
-            m->rhobar[(size_t)e * N + i] = 0.5 * (rho[i] + rho[neighbour(i, ndim, m->n, e, +1)]);
+            m->rhobar[(size_t)e * N + i] = colloc ? rho[i]
+                                                  : 0.5 * (rho[i] + rho[neighbour(i, ndim, m->n, e, +1)]);
 
     /* diagonal blocks of the row-scaled staggered system */
     for (int e = 0; e < ndim; ++e)
@@ -369,9 +378,19 @@ int orc_create(int ndim, const int64_t *n, double dx, double omega, int pml,
         }
         m->sh[d] = malloc(sizeof(cplx) * len);
         for (int j = 0; j < len; ++j) m->sh[d][j] = cexp(I * m->kv[d][j] * dx / 2.0);
+        m->kd[d] = malloc(sizeof(double) * len);
+        for (int j = 0; j < len; ++j)
+            m->kd[d][j] = (len % 2 == 0 && j == len / 2) ? 0.0 : m->kv[d][j];
     }
     *out = m;
     return 0;
+}
+
+int orc_create(int ndim, const int64_t *n, double dx, double omega, int pml,
+               double gmax, double beta, double nu, int shift_rule,
+               const double *c, const double *rho, const double *alpha, void **out)
+{
+    return orc_create2(ndim, n, dx, omega, pml, gmax, beta, nu, shift_rule, 0, c, rho, alpha, out);
 }
 
 /* a1 (re, im), a2 (re, im), lam1, lam2, beta, nu */
@@ -434,9 +453,19 @@ int orc_apply_A(void *h, int adjoint, const double *xi_, double *out_)
         cplx S[3];
         kvec(m, i, k, S);
         cplx pp = sp[(size_t)D * N + i], acc = 0;
-        for (int e = 0; e < D; ++e) {
-            dr[(size_t)e * N + i] = sgn * I * k[e] * S[e] * pp;
-            acc += sgn * I * k[e] * conj(S[e]) * sp[(size_t)e * N + i];
+        if (m->colloc) {          /* i k, Nyquist bin of the odd derivative zeroed */
+            int64_t ix[3];
+            unravel(i, D, m->n, ix);
+            for (int e = 0; e < D; ++e) {
+                double kd = m->kd[e][ix[e]];
+                dr[(size_t)e * N + i] = sgn * I * kd * pp;
+                acc += sgn * I * kd * sp[(size_t)e * N + i];
+            }
+        } else {
+            for (int e = 0; e < D; ++e) {
+                dr[(size_t)e * N + i] = sgn * I * k[e] * S[e] * pp;
+                acc += sgn * I * k[e] * conj(S[e]) * sp[(size_t)e * N + i];
+            }
         }
         dr[(size_t)D * N + i] = acc;
     }
@@ -477,15 +506,49 @@ static void propagator(const orc_medium *m, const double *k, const cplx *S, cplx
     M[D * F + D] = m->lam2 * al1 / mu;
 }
 
+/* Collocated (L+I)^{-1} of App. B (first matrix) with k the collocated
+ * derivative wavenumbers:
+ *   M = (1/mu) [[ lam1/alpha1 (mu I - k k^T), -i s k ], [ -i s k^T, lam2 alpha1 ]]. */
+static void propagator_colloc(const orc_medium *m, const double *k, cplx *M)
+{
+    int D = m->ndim, F = D + 1;
+    cplx al1 = m->a1 + m->lam1, al2 = m->a2 + m->lam2;
+    double kk = 0;
+    for (int e = 0; e < D; ++e) kk += k[e] * k[e];
+    cplx mu = kk + al1 * al2;
+    double s = sqrt(m->lam1 * m->lam2);
+    for (int e = 0; e < D; ++e) {
+        for (int f = 0; f < D; ++f)
+            M[e * F + f] = m->lam1 * ((e == f ? mu : 0.0) - k[e] * k[f]) / (al1 * mu);
+        M[e * F + D] = -I * s * k[e] / mu;
+        M[D * F + e] = -I * s * k[e] / mu;
+    }
+    M[D * F + D] = m->lam2 * al1 / mu;
+}
+
+static void propagator_any(const orc_medium *m, int64_t idx, cplx *M)
+{
+    double k[3];
+    cplx S[3];
+    kvec(m, idx, k, S);
+    if (m->colloc) {
+        int64_t ix[3];
+        unravel(idx, m->ndim, m->n, ix);
+        double kd[3];
+        for (int e = 0; e < m->ndim; ++e) kd[e] = m->kd[e][ix[e]];
+        propagator_colloc(m, kd, M);
+    } else {
+        propagator(m, k, S, M);
+    }
+}
+
 /* Write the propagator at flat k index idx (for tests); adjoint gives M^H. */
 void orc_propagator_at(void *h, int64_t idx, int adjoint, double *out_)
 {
     orc_medium *m = h;
     int F = m->ndim + 1;
-    cplx M[16], S[3], *out = (cplx *)out_;
-    double k[3];
-    kvec(m, idx, k, S);
-    propagator(m, k, S, M);
+    cplx M[16], *out = (cplx *)out_;
+    propagator_any(m, idx, M);
     for (int r = 0; r < F; ++r)
         for (int c = 0; c < F; ++c)
             out[r * F + c] = adjoint ? conj(M[c * F + r]) : M[r * F + c];
@@ -571,10 +634,8 @@ int orc_solve(void *h, int adjoint, const double *shat_, double tol, int64_t max
         for (int f = 0; f < F; ++f) orc_fft(D, m->n, (double *)(w + (size_t)f * N), -1);
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < N; ++i) {
-            double k[3];
-            cplx M[16], S[3], v[4], r[4];
-            kvec(m, i, k, S);
-            propagator(m, k, S, M);
+            cplx M[16], v[4], r[4];
+            propagator_any(m, i, M);
             for (int f = 0; f < F; ++f) v[f] = w[(size_t)f * N + i];
             for (int a = 0; a < F; ++a) {
                 cplx acc = 0;
@@ -664,8 +725,14 @@ void orc_gradient(void *h, const double *s_, const double *xi_, const double *la
         gc[i] = creal(core * dq_dc);
         galpha[i] = creal(core * dq_dal);
         double gr = creal(core * dq_drho);
-        /* velocity rows: rhobar_eta at x and at x - e_eta depend on rho(x) */
+        /* velocity rows: rhobar_eta at x and at x - e_eta depend on rho(x)
+         * (collocated: the velocity rows at x only, weight 1) */
         for (int e = 0; e < D; ++e) {
+            if (m->colloc) {
+                size_t a = (size_t)e * N + i;
+                gr += creal(conj(lam[a]) * (s[a] - (I * w + m->gams[a]) * xi[a]));
+                continue;
+            }
             int64_t j = neighbour(i, D, m->n, e, -1);
             size_t a = (size_t)e * N + i, b = (size_t)e * N + j;
             cplx ta = conj(lam[a]) * (s[a] - (I * w + m->gams[a]) * xi[a]);

@@ -30,6 +30,10 @@ def lib():
                                  C.c_double, C.c_double, C.c_int, dp, dp, dp,
                                  C.POINTER(C.c_void_p)]
         L.orc_create.restype = C.c_int
+        L.orc_create2.argtypes = [C.c_int, i64p, C.c_double, C.c_double, C.c_int, C.c_double,
+                                  C.c_double, C.c_double, C.c_int, C.c_int, dp, dp, dp,
+                                  C.POINTER(C.c_void_p)]
+        L.orc_create2.restype = C.c_int
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_get_scalars.argtypes = [C.c_void_p, dp]
         L.orc_set_scalars.argtypes = [C.c_void_p, dp]
@@ -70,7 +74,7 @@ def mec(points: np.ndarray):
 
 class OracleMedium:
     def __init__(self, shape, dx, omega, c, rho, alpha, pml=16, gmax=0.0,
-                 beta=0.95, nu=0.9, shift_rule=0):
+                 beta=0.95, nu=0.9, shift_rule=0, collocated=False):
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.ncell = int(np.prod(self.shape))
@@ -81,10 +85,10 @@ class OracleMedium:
         self._alpha = np.ascontiguousarray(alpha, dtype=np.float64).reshape(self.shape)
         n = np.array(self.shape, dtype=np.int64)
         h = C.c_void_p()
-        rc = lib().orc_create(self.ndim, n.ctypes.data_as(C.POINTER(C.c_int64)), self.dx,
-                              self.omega, int(pml), float(gmax), float(beta), float(nu),
-                              int(shift_rule), _dp(self._c), _dp(self._rho), _dp(self._alpha),
-                              C.byref(h))
+        rc = lib().orc_create2(self.ndim, n.ctypes.data_as(C.POINTER(C.c_int64)), self.dx,
+                               self.omega, int(pml), float(gmax), float(beta), float(nu),
+                               int(shift_rule), int(bool(collocated)), _dp(self._c), _dp(self._rho),
+                               _dp(self._alpha), C.byref(h))
         if rc != 0:
             raise ValueError("oracle rejected the medium")
         self._h = h

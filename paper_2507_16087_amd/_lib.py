@@ -43,7 +43,8 @@ EXPORTS = [
 class Grid(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n", C.c_int64 * 3), ("dx", C.c_double),
                 ("omega", C.c_double), ("pml_cells", C.c_int32), ("pml_gamma_max", C.c_double),
-                ("beta", C.c_double), ("nu", C.c_double), ("shift_rule", C.c_int32)]
+                ("beta", C.c_double), ("nu", C.c_double), ("shift_rule", C.c_int32),
+                ("collocated", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -22,7 +22,7 @@ namespace cbs {
 // kernels (cbs_kernels.hip)
 template <typename T>
 hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
-                       int pcols, bool wide, hipStream_t st);
+                       int pcols, bool wide, int variant, hipStream_t st);
 template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st);
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st);
@@ -44,7 +44,7 @@ hipError_t launch_gradient(const Geom& g, const double* c, const double* rho, co
                            const cx<double>* q, const double* const* gcen, const double* const* gst, double gmax,
                            double omega, const cx<double>* sp, const cx<double>* su, const cx<double>* p,
                            const cx<double>* u, const cx<double>* lp, const cx<double>* lu, double* gc,
-                           double* grho, double* galpha, hipStream_t st);
+                           double* grho, double* galpha, int collocated, hipStream_t st);
 int plan_tpc(int n, bool wide);
 bool plan_has_wide(int n);
 enum { MODE_CBS = 0, MODE_APPLY = 1 };
@@ -76,6 +76,7 @@ struct Pass {
     int n;
     int pcols;
     bool wide;
+    int variant;   // propagator: 1 = all fields' FFT stages share each LDS exchange
 };
 
 struct PassSet {
@@ -412,7 +413,7 @@ hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int 
         if (timed && timing_begin(*tp, group * 8 + (i == ps.count - 1 ? 4 : i), st) != hipSuccess)
             return hipErrorUnknown;
         hipError_t e = launch_pass<T>(kind, mode, pro ? starts : all, pro ? nstart : nall, g, p.axis, p.n, p.pcols,
-                                      p.wide, st);
+                                      p.wide, p.variant, st);
         if (e != hipSuccess) return e;
         if (timed && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
     }
@@ -437,15 +438,24 @@ hipError_t run_passes(cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T
 // every medium of one shape runs the same kernels (results of a solve do not
 // depend on which other solves ran first).  CBS_AUTOTUNE=0 keeps the defaults.
 struct TuneKey {
-    int ndim, n0, n1, n2, fp64;
+    int ndim, n0, n1, n2, fp64, prop_variant;
     bool operator<(const TuneKey& o) const {
-        return std::tie(ndim, n0, n1, n2, fp64) < std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64);
+        return std::tie(ndim, n0, n1, n2, fp64, prop_variant) <
+               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant);
     }
 };
+
+// CBS_PROP_VARIANT=0 or 1 pins the propagator pass to one variant (per-field
+// LDS exchanges, or all fields sharing each exchange); unset, both compete.
+int forced_prop_variant() {
+    const char* e = std::getenv("CBS_PROP_VARIANT");
+    if (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) return e[0] - '0';
+    return -1;
+}
 std::mutex g_tune_mu;
 std::map<TuneKey, PassSet> g_tune_cache;
 
-std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
+std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64, int prop_variant) {
     std::vector<Pass> out;
     const int last = g.ndim - 1;
     const bool lastaxis = base.kind == 0 || base.kind == 1;
@@ -468,7 +478,11 @@ std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
             Pass p = base;
             p.wide = wide != 0;
             p.pcols = pc;
-            out.push_back(p);
+            for (int v = 0; v < (base.kind == 4 ? 2 : 1); ++v) {
+                if (base.kind == 4 && prop_variant >= 0 && v != prop_variant) continue;
+                p.variant = v;
+                out.push_back(p);
+            }
         }
     }
     return out;
@@ -485,11 +499,13 @@ float time_pass(cbs_medium_s* m, int kind, const Slot<T>* dslot, const Pass& p, 
     float ms = -1.f;
     bool ok = true;
     for (int i = 0; i < 2 && ok; ++i)
-        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, st) == hipSuccess;
+        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, p.variant, st) ==
+             hipSuccess;
     const int reps = 6;
     ok = ok && hipEventRecord(a, st) == hipSuccess;
     for (int i = 0; i < reps && ok; ++i)
-        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, st) == hipSuccess;
+        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, p.variant, st) ==
+             hipSuccess;
     ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
     if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms /= reps;
     else ms = -1.f;
@@ -514,7 +530,7 @@ cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T
         const int kind = (i == ps.count - 1) ? 5 : ps.p[i].kind;
         float best = -1.f;
         Pass pick = ps.p[i];
-        for (const Pass& c : pass_candidates(m->g, ps.p[i], fp64)) {
+        for (const Pass& c : pass_candidates(m->g, ps.p[i], fp64, forced_prop_variant())) {
             const float t = time_pass<T>(m, kind, dslot, c, st);
             if (t > 0.f && (best < 0.f || t < best)) {
                 best = t;
@@ -582,7 +598,13 @@ bool autotune_enabled() {
 // Tune the pass sets this precision uses, on the caller's workspace (its
 // contents are scratch here), or take them from the process cache.
 cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
-    if (!autotune_enabled()) return CBS_OK;
+    if (!autotune_enabled()) {
+        const int v = forced_prop_variant();
+        for (PassSet* ps : {&m->ps64, &m->ps32})
+            for (int i = 0; i < ps->count; ++i)
+                if (ps->p[i].kind == 4) ps->p[i].variant = v > 0 ? v : 0;
+        return CBS_OK;
+    }
     const Layout L = layout_for(m, prec);
     const Geom& g = m->g;
     for (int fp64 = 1; fp64 >= 0; --fp64) {
@@ -590,7 +612,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         bool& done = fp64 ? m->tuned64 : m->tuned32;
         if (done) continue;
         PassSet& ps = fp64 ? m->ps64 : m->ps32;
-        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64};
+        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_prop_variant()};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(key);
@@ -631,6 +653,7 @@ cbs_status validate_grid(const cbs_grid* g) {
     if (!(beta > 0) || !std::isfinite(beta)) return CBS_E_INVALID;
     if (!(nu > 0) || !std::isfinite(nu)) return CBS_E_INVALID;
     if (g->shift_rule != 0 && g->shift_rule != 1) return CBS_E_INVALID;
+    if (g->collocated != 0 && g->collocated != 1) return CBS_E_INVALID;
     return CBS_OK;
 }
 
@@ -696,8 +719,9 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
         prof_c[d].assign(g.n[d], 0.0);
         prof_s[d].assign(g.n[d], 0.0);
         if (d >= D) continue;
+        const double half = grid->collocated ? 0.0 : 0.5;   // velocity rows' position
         for (int i = 0; i < g.n[d]; ++i) {
-            const double rc = layer_frac(i, g.n[d], L), rs = layer_frac(i + 0.5, g.n[d], L);
+            const double rc = layer_frac(i, g.n[d], L), rs = layer_frac(i + half, g.n[d], L);
             prof_c[d][i] = rc * rc;
             prof_s[d][i] = rs * rs;
         }
@@ -723,7 +747,7 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
         Dp[i] = cd(gam, w) * q[i];
         for (int e = 0; e < D; ++e) {
             const int64_t nb = (ix[e] + 1 < g.n[e]) ? i + stride[e] : i - (int64_t)(g.n[e] - 1) * stride[e];
-            const double rbar = 0.5 * (hr[i] + hr[nb]);
+            const double rbar = grid->collocated ? hr[i] : 0.5 * (hr[i] + hr[nb]);
             rb[(size_t)e * N + i] = rbar;
             double gs = 0.0;
             for (int d = 0; d < D; ++d) gs += (d == e) ? prof_s[d][ix[d]] : prof_c[d][ix[d]];
@@ -812,6 +836,11 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
             const int fidx = (j < (n + 1) / 2) ? j : j - n;   // FFT order
             kv[j] = d < D ? 2.0 * M_PI * fidx / (n * dx) : 0.0;
             sh[j] = {std::cos(kv[j] * dx / 2), std::sin(kv[j] * dx / 2)};
+            if (grid->collocated) {
+                // collocated derivative symbol i k, Nyquist bin zeroed, no shift
+                if (n % 2 == 0 && j == n / 2) kv[j] = 0.0;
+                sh[j] = {1.0, 0.0};
+            }
             const double ang = -2.0 * M_PI * (double)j / (double)n;
             tw[j] = {std::cos(ang), std::sin(ang)};
             kv32[j] = (float)kv[j];
@@ -1187,7 +1216,7 @@ cbs_status cbs_gradient(cbs_medium m, const void* s_p, const void* s_u, const vo
                               static_cast<const cx<double>*>(s_p), static_cast<const cx<double>*>(s_u),
                               static_cast<const cx<double>*>(p), static_cast<const cx<double>*>(u),
                               static_cast<const cx<double>*>(lp), static_cast<const cx<double>*>(lu), g_c, g_rho,
-                              g_alpha, st));
+                              g_alpha, m->grid.collocated, st));
         HIPOK(hipStreamSynchronize(st));
         return CBS_OK;
     }
@@ -1218,7 +1247,7 @@ cbs_status cbs_gradient(cbs_medium m, const void* s_p, const void* s_u, const vo
     if (rc == CBS_OK &&
         launch_gradient(g, m->c64, m->rho64, m->alpha64, m->q64, gcen, gst, m->gmax, m->grid.omega, dsp,
                         s_u ? dsu : nullptr, dp, u ? du : nullptr, dlp, lu ? dlu : nullptr, dgc, dgr, dga,
-                        st) != hipSuccess)
+                        m->grid.collocated, st) != hipSuccess)
         rc = CBS_E_DEVICE;
     if (rc == CBS_OK) {
         if (g_c && hipMemcpyAsync(g_c, dgc, rN, hipMemcpyDeviceToHost, st) != hipSuccess) rc = CBS_E_DEVICE;
@@ -1239,7 +1268,7 @@ cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]) {
         out[4 * i + 0] = have ? ps.p[i].kind : -1;
         out[4 * i + 1] = have ? ps.p[i].n : 0;
         out[4 * i + 2] = have ? ps.p[i].pcols : 0;
-        out[4 * i + 3] = have ? (ps.p[i].wide ? 1 : 0) : 0;
+        out[4 * i + 3] = have ? ((ps.p[i].wide ? 1 : 0) | (ps.p[i].variant << 1)) : 0;
     }
     return CBS_OK;
 }

@@ -284,6 +284,44 @@ __device__ __forceinline__ void fft_regs(cx<T>* v, cx<T>* lds, int ldp, int col,
     }
 }
 
+// The same transform on the first F of NF register arrays at once, each with
+// its own LDS region (field_elems elements apart): one barrier per stage
+// exchange covers every field.
+template <class P, int DIR, int NF, typename T>
+__device__ __forceinline__ void fft_regs_multi(cx<T> (*v)[P::E], int F, cx<T>* lds, int field_elems, int ldp,
+                                               int col, int lane, const cx<T>* __restrict__ tw) {
+    using Q = Seq<P, DIR>;
+    constexpr int N = P::N, TPC = P::TPC;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+        if (f < F) stage_compute<N, Q::r(0), 1, TPC, DIR>(v[f], lane, tw);
+    if constexpr (P::S >= 2) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < F) lds_scatter<N, Q::r(0), 1, TPC, COLS>(v[f], lds + f * field_elems, ldp, col, lane);
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < F) {
+                lds_gather<N, Q::r(1), TPC, COLS>(v[f], lds + f * field_elems, ldp, col, lane);
+                stage_compute<N, Q::r(1), Q::ns(1), TPC, DIR>(v[f], lane, tw);
+            }
+    }
+    if constexpr (P::S >= 3) {
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < F) lds_scatter<N, Q::r(1), Q::ns(1), TPC, COLS>(v[f], lds + f * field_elems, ldp, col, lane);
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < F) {
+                lds_gather<N, Q::r(2), TPC, COLS>(v[f], lds + f * field_elems, ldp, col, lane);
+                stage_compute<N, Q::r(2), Q::ns(2), TPC, DIR>(v[f], lane, tw);
+            }
+    }
+}
+
 // Index of element (lane, b, r) of the last stage in natural order.
 template <class P, int DIR>
 __device__ __forceinline__ int out_index(int lane, int b, int r) {
@@ -593,7 +631,7 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 // FFT.  MODE CBS applies (L+I)^{-1} of App. B.1 (rank-one form, conjugate
 // transpose for the adjoint); MODE APPLY applies the scaled staggered
 // derivative block of L (negated for the adjoint).  1/prod(n) is folded in.
-template <class P, int MODE, typename T>
+template <class P, int MODE, bool MULTI, typename T>
 __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols,
                                               int ldp, int64_t es, int64_t ostride, int nlast_tiles, int xg) {
     extern __shared__ unsigned char smem_raw[];
@@ -609,8 +647,9 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     const int il = (tile % nlast_tiles) * pcols + col;              // index along the last axis
     cx<T>* __restrict__ wt = s.w + (int64_t)io * ostride + (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
-    // LDS: tile | twiddles (N) | k0 S0 (N) | k0 (N)
-    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tile_bytes<T>((size_t)N * ldp));
+    // LDS: tile (one per field when MULTI) | twiddles (N) | k0 S0 (N) | k0 (N)
+    const int field_elems = (int)(tile_bytes<T>((size_t)N * ldp) / sizeof(cx<T>));
+    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + (size_t)(MULTI ? 4 : 1) * field_elems * sizeof(cx<T>));
     cx<T>* g0_l = tw_l + N;
     T* k0_l = reinterpret_cast<T*>(g0_l + N);
     for (int i = tid; i < N; i += blockDim.x) {
@@ -651,11 +690,15 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
                     v[f][b * R0 + r] = wf[(uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32];
         }
     }
+    if constexpr (MULTI) {
+        fft_regs_multi<P, -1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+    } else {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        if (f < F) {
-            if (f > 0) __syncthreads();
-            fft_regs<P, -1>(v[f], lds, ldp, col, lane, tw);
+        for (int f = 0; f < 4; ++f) {
+            if (f < F) {
+                if (f > 0) __syncthreads();
+                fft_regs<P, -1>(v[f], lds, ldp, col, lane, tw);
+            }
         }
     }
 
@@ -711,11 +754,17 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     // inverse FFT from the registers and store
     using QI = Seq<P, 1>;
     constexpr int RL = QI::r(P::S - 1);
+    if constexpr (MULTI) {
+        __syncthreads();
+        fft_regs_multi<P, 1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+    }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         if (f < F) {
-            __syncthreads();
-            fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
+            if constexpr (!MULTI) {
+                __syncthreads();
+                fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
+            }
             cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
 #pragma unroll
             for (int b = 0; b < N / (RL * P::TPC); ++b)
@@ -899,7 +948,7 @@ __global__ void k_gradient(Geom g, const double* c, const double* rho, const dou
                            const double* gst2, double gmax, double omega, const cx<double>* sp,
                            const cx<double>* su, const cx<double>* p, const cx<double>* u,
                            const cx<double>* lp, const cx<double>* lu, double* gc, double* grho,
-                           double* galpha) {
+                           double* galpha, int collocated) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.ncell) return;
     int ix[3];
@@ -921,7 +970,14 @@ __global__ void k_gradient(Geom g, const double* c, const double* rho, const dou
     if (galpha) galpha[i] = cmul(core, dq_dal).re;
     if (grho) {
         double gr = cmul(core, dq_drho).re;
-        if (u && lu) {
+        if (u && lu && collocated) {
+            // collocated: the velocity rows at this cell carry rho(x) itself
+            for (int e = 0; e < g.ndim; ++e) {
+                const int64_t k = (int64_t)e * g.ncell + i;
+                const cx<double> sv = su ? su[k] : cx<double>{0.0, 0.0};
+                gr += cmulc(sv - cmul(iwg, u[k]), lu[k]).re;
+            }
+        } else if (u && lu) {
             for (int e = 0; e < g.ndim; ++e) {
                 // rhobar_e at this cell and at the cell one step back along e
                 int jx[3] = {ix[0], ix[1], ix[2]};
@@ -979,12 +1035,16 @@ int plan_tpc(int n, bool wide) {
 
 bool plan_has_wide(int n) { return n == 64 || n == 128 || n == 256; }
 
+// LDS one work-group may hold on gfx950 (160 KiB per compute unit); larger
+// configurations are refused before launch.
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
 // Launch one pass.  kind: 0 last-axis forward with prologue, 1 last-axis
 // inverse with epilogue, 5 both fused across iterations, 2 strided forward,
 // 3 strided inverse, 4 axis-0 propagator.
 template <typename T, class P>
 static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis,
-                              int pcols, hipStream_t st) {
+                              int pcols, int variant, hipStream_t st) {
     const int N = P::N;
     const int ldp = pcols + 1;
     // tile + twiddles + (propagator) k0 S0 and k0 tables
@@ -999,6 +1059,7 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         const dim3 blk(pcols * P::TPC);
         const size_t lr = std::max(tile_bytes<T>((size_t)pcols * lds_pitch<ROWS>(N, 0)), (size_t)(64 * sizeof(double))) +
                           (size_t)N * (sizeof(cx<T>) + sizeof(T));
+        if (lr > kMaxLdsBytes) return hipErrorInvalidConfiguration;
         if (kind == 0) {
             if (mode == CBS)
                 hipLaunchKernelGGL((k_lastaxis<P, CBS, FIRST, T>), grid, blk, lr, st, slots, g, pcols);
@@ -1034,13 +1095,23 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         if (xg < 1 || nlast_tiles % xg) xg = 1;
         if (kind == 4) {
             const dim3 grid(tiles, 1, nslots);
-            if (mode == CBS)
-                hipLaunchKernelGGL((k_prop<P, CBS, T>), grid, block, lds, st, slots, g, pcols, ldp, es, ostride,
-                                   nlast_tiles, xg);
+            const bool multi = variant == 1;
+            const size_t lp = multi ? lds + 3 * tile_bytes<T>((size_t)N * ldp) : lds;
+            if (lp > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+            if (mode == CBS && multi)
+                hipLaunchKernelGGL((k_prop<P, CBS, true, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
+                                   ostride, nlast_tiles, xg);
+            else if (mode == CBS)
+                hipLaunchKernelGGL((k_prop<P, CBS, false, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
+                                   ostride, nlast_tiles, xg);
+            else if (multi)
+                hipLaunchKernelGGL((k_prop<P, APPLY, true, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
+                                   ostride, nlast_tiles, xg);
             else
-                hipLaunchKernelGGL((k_prop<P, APPLY, T>), grid, block, lds, st, slots, g, pcols, ldp, es, ostride,
-                                   nlast_tiles, xg);
+                hipLaunchKernelGGL((k_prop<P, APPLY, false, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
+                                   ostride, nlast_tiles, xg);
         } else {
+            if (lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
             const dim3 grid(tiles, F, nslots);
             const int skip = mode == CBS ? 1 : 0;
             if (kind == 2)
@@ -1056,18 +1127,19 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
 
 template <typename T>
 hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
-                       int pcols, bool wide, hipStream_t st) {
+                       int pcols, bool wide, int variant, hipStream_t st) {
 #define LAUNCH_CASE(N_, A, B, C, T_) \
-    if (n == N_) return launch_plan<T, Plan<N_, A, B, C, T_>>(kind, mode, slots, nslots, g, axis, pcols, st);
+    if (n == N_)                     \
+        return launch_plan<T, Plan<N_, A, B, C, T_>>(kind, mode, slots, nslots, g, axis, pcols, variant, st);
     if (wide) { CBS_PLANS_WIDE(LAUNCH_CASE) }
     CBS_PLANS(LAUNCH_CASE)
 #undef LAUNCH_CASE
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_pass<float>(int, int, const Slot<float>*, int, const Geom&, int, int, int, bool,
+template hipError_t launch_pass<float>(int, int, const Slot<float>*, int, const Geom&, int, int, int, bool, int,
                                        hipStream_t);
-template hipError_t launch_pass<double>(int, int, const Slot<double>*, int, const Geom&, int, int, int, bool,
+template hipError_t launch_pass<double>(int, int, const Slot<double>*, int, const Geom&, int, int, int, bool, int,
                                         hipStream_t);
 
 template <typename T>
@@ -1142,9 +1214,10 @@ hipError_t launch_gradient(const Geom& g, const double* c, const double* rho, co
                            const cx<double>* q, const double* const* gcen, const double* const* gst, double gmax,
                            double omega, const cx<double>* sp, const cx<double>* su, const cx<double>* p,
                            const cx<double>* u, const cx<double>* lp, const cx<double>* lu, double* gc,
-                           double* grho, double* galpha, hipStream_t st) {
+                           double* grho, double* galpha, int collocated, hipStream_t st) {
     hipLaunchKernelGGL(k_gradient, grid1(g.ncell), dim3(256), 0, st, g, c, rho, alpha, q, gcen[0], gcen[1],
-                       gcen[2], gst[0], gst[1], gst[2], gmax, omega, sp, su, p, u, lp, lu, gc, grho, galpha);
+                       gcen[2], gst[0], gst[1], gst[2], gmax, omega, sp, su, p, u, lp, lu, gc, grho, galpha,
+                       collocated);
     return hipGetLastError();
 }
 

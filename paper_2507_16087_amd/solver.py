@@ -69,7 +69,7 @@ class Medium:
 
     def __init__(self, shape: Sequence[int], dx: float, omega: float, c, rho, alpha,
                  pml: int = 16, gamma_max: float = 0.0, beta: float = 0.95, nu: float = 0.9,
-                 shift_rule: int = 0, stream=None):
+                 shift_rule: int = 0, collocated: bool = False, stream=None):
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.ncell = int(np.prod(self.shape))
@@ -81,6 +81,7 @@ class Medium:
             g.n[d] = self.shape[d] if d < self.ndim else 1
         g.dx, g.omega, g.pml_cells, g.pml_gamma_max = self.dx, self.omega, int(pml), float(gamma_max)
         g.beta, g.nu, g.shift_rule = float(beta), float(nu), int(shift_rule)
+        g.collocated = int(bool(collocated))
         self.grid = g
         if _is_tensor(c):
             arrs = [t.contiguous().to(_torch().float64) for t in (c, rho, alpha)]
@@ -117,6 +118,16 @@ class Medium:
     def set_scalars(self, a1, a2, lam1, lam2):
         v = (C.c_double * 6)(a1.real, a1.imag, a2.real, a2.imag, lam1, lam2)
         L.check(L.lib().cbs_set_scalars(self._h, v), "cbs_set_scalars")
+
+    def pass_config(self, prec="fp64") -> list:
+        """Pass plans of one iteration at this precision, in launch order (tuned
+        by the first solve): kind, axis length, columns per work-group, wide
+        radix split, fields sharing each LDS exchange (propagator only)."""
+        cfg = (C.c_int32 * 20)()
+        L.check(L.lib().cbs_pass_config(self._h, PREC[prec], cfg), "cbs_pass_config")
+        return [dict(kind=cfg[4 * i], n=cfg[4 * i + 1], cols=cfg[4 * i + 2],
+                     wide=cfg[4 * i + 3] & 1, shared_lds=(cfg[4 * i + 3] >> 1) & 1)
+                for i in range(5) if cfg[4 * i] >= 0]
 
     def workspace_bytes(self, prec="fp64", batch=1) -> int:
         b = C.c_size_t()

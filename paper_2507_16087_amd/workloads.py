@@ -17,6 +17,8 @@ Workloads (all SI units; alpha in Np/m):
   noise, insonified by a focused bowl (64 mm radius of curvature, 60 mm
   aperture) rasterised as a surface of point sources.  It stands in for the
   paper's transcranial benchmark, whose skull mesh is not used here.
+* ``disks2d``    -- the paper's 2-D disks example (256^2, 0.5 mm, 500 kHz,
+  inclusions of c 3500, rho 3000, alpha 10 dB/cm, line source at the top).
 * ``requests``   -- a Poisson stream of mixed-size random3d solves.
 * ``inversion``  -- the random3d medium with 8 shots on one face, 128
   receivers on the opposite face and a smooth +/-3 % bump for the data model.
@@ -110,6 +112,39 @@ def disc2d(n: int = 128) -> Problem:
     src = np.array([(n // 4) * n + n // 2], dtype=np.int64)   # cell (32, 64)
     return Problem("disc2d", 2, shape, dx, 2 * np.pi * f, c, rho, alpha, src,
                    np.array([1.0 + 0j]))
+
+
+def disks2d(n: int = 256) -> Problem:
+    """2-D example of the paper's first experiment: 256 x 256 grid, 0.5 mm,
+    500 kHz, water background, circular inclusions of c 3500 m/s, rho 3000
+    kg/m^3 and alpha 10 dB/cm, and a planar line source near the top edge.
+    The paper gives no positions or sizes; here one disc of each property
+    (radius 16 mm) sits on the axis below the source and the three overlap
+    pairwise in lens-shaped regions."""
+    f = 5e5
+    dx = 0.5e-3
+    shape = (n, n)
+    c = np.full(shape, WATER_C)
+    rho = np.full(shape, WATER_RHO)
+    a_db = np.zeros(shape)
+    i0, i1 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    s = n / 256.0
+    rad = 32 * s
+    centres = {"c": (112 * s, 96 * s), "rho": (112 * s, 160 * s), "alpha": (160 * s, 128 * s)}
+    for key, (y, x) in centres.items():
+        inside = (i0 - y) ** 2 + (i1 - x) ** 2 < rad ** 2
+        if key == "c":
+            c[inside] = 3500.0
+        elif key == "rho":
+            rho[inside] = 3000.0
+        else:
+            a_db[inside] = 10.0
+    alpha = a_db * 100.0 / DB_PER_NEPER          # 10 dB/cm at 500 kHz -> Np/m
+    row = int(round(40 * s))
+    cols = np.arange(int(48 * s), int(208 * s))
+    idx = np.ravel_multi_index((np.full(cols.size, row), cols), shape).astype(np.int64)
+    return Problem(f"disks2d_{n}", 2, shape, dx, 2 * np.pi * f, c, rho, alpha, idx,
+                   np.ones(idx.size, dtype=np.complex128))
 
 
 def random_medium(shape, seed: int, f_hz: float, sigma: float = 4.0):

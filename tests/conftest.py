@@ -13,6 +13,30 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: CPU test that takes tens of seconds")
 
 
+def progress(msg: str) -> None:
+    """Progress line for long GPU tests: straight to the terminal (past pytest's
+    output capture) and appended to gpurun_out/progress.log."""
+    import sys
+    import time
+    line = f"[{time.strftime('%H:%M:%S')}] {msg}"
+    try:
+        sys.__stderr__.write(line + "\n")
+        sys.__stderr__.flush()
+    except Exception:
+        pass
+    try:
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(ROOT, "gpurun_out", "progress.log"), "a") as f:
+            f.write(line + "\n")
+    except OSError:
+        pass
+
+
+@pytest.fixture(scope="session")
+def report():
+    return progress
+
+
 @pytest.fixture(scope="session")
 def orc():
     from oracle import core

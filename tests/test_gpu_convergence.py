@@ -1,0 +1,77 @@
+"""Convergence study (the paper's iterations-vs-contrast figure, Discussion):
+a central disc of added sound speed or density in water, iterations of the
+FP64 solver to a relative update of 1e-6.  The paper's curves are not
+recoverable, so the checks are self-consistent: the GPU needs exactly the
+oracle's iteration count for the same medium; more contrast (in c or in rho)
+needs more iterations; the minimum-enclosing-circle shift needs no more
+iterations than the component-wise median; a stronger absorbing layer slows
+convergence.  The measured table is printed (pytest -s) and kept in the design doc.
+"""
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+N = 128
+DX = 0.25e-3
+OMEGA = 2 * np.pi * 1e6
+
+
+@pytest.fixture(scope="module")
+def cbs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_16087_amd import solver
+    return solver
+
+
+def _disc(dc=0.0, drho=0.0):
+    shape = (N, N)
+    c = np.full(shape, 1500.0)
+    rho = np.full(shape, 1000.0)
+    i0, i1 = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    inside = (i0 - N // 2) ** 2 + (i1 - N // 2) ** 2 < 24 ** 2
+    c[inside] += dc
+    rho[inside] += drho
+    sp = np.zeros(shape, complex)
+    sp[20, N // 2] = 1.0
+    return c, rho, np.zeros(shape), sp
+
+
+def _iters(cbs, dc=0.0, drho=0.0, rule=0, gmax=0.0):
+    c, rho, alpha, sp = _disc(dc, drho)
+    m = cbs.Medium((N, N), DX, OMEGA, c, rho, alpha, pml=16, shift_rule=rule, gamma_max=gmax)
+    _, _, info = cbs.solve(m, sp, tol=1e-6, max_iter=400000, check_every=128, want_u=False)
+    assert info["converged"]
+    return info["iterations"]
+
+
+def test_iteration_count_matches_oracle(cbs, orc):
+    c, rho, alpha, sp = _disc(500.0, 1000.0)
+    om = orc.OracleMedium((N, N), DX, OMEGA, c, rho, alpha, pml=16)
+    _, info = om.solve(om.source_hat(om.pressure_source(sp)), tol=1e-6, max_iter=400000)
+    assert info["iterations"] == _iters(cbs, 500.0, 1000.0)
+
+
+def test_iterations_grow_with_contrast(cbs):
+    rows = []
+    its_c = [_iters(cbs, dc=v) for v in (0.0, 250.0, 500.0, 1000.0, 2000.0)]
+    its_r = [_iters(cbs, drho=v) for v in (0.0, 500.0, 1000.0, 2000.0, 4000.0)]
+    rows.append(("sound speed +0/250/500/1000/2000 m/s", its_c))
+    rows.append(("density +0/500/1000/2000/4000 kg/m^3", its_r))
+    for name, its in rows:
+        print(f"{name}: {its}")
+    assert all(b >= a for a, b in zip(its_c, its_c[1:])) and its_c[-1] > 2 * its_c[0]
+    assert all(b >= a for a, b in zip(its_r, its_r[1:])) and its_r[-1] > its_r[0]
+
+
+def test_shift_rule_and_layer_strength(cbs):
+    mec = _iters(cbs, 500.0, 1000.0, rule=0)
+    med = _iters(cbs, 500.0, 1000.0, rule=1)
+    print(f"minimum enclosing circle: {mec} iterations, median: {med}")
+    assert mec <= med
+    weak = _iters(cbs, 500.0, 0.0, gmax=0.5 * OMEGA)
+    strong = _iters(cbs, 500.0, 0.0, gmax=3.0 * OMEGA)
+    print(f"layer gamma_max 0.5 w: {weak} iterations, 3 w: {strong}")
+    assert strong > weak

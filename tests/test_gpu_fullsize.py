@@ -42,7 +42,8 @@ def test_random128_fp64_iterates(cbs, orc):
 
 
 @pytest.fixture(scope="module")
-def shell(cbs, orc):
+def shell(cbs, orc, report):
+    report("shell3d 256^3: building workload, GPU medium and oracle medium")
     pr = W.shell3d(256)
     gm = cbs.Medium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
     om = orc.OracleMedium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
@@ -50,8 +51,9 @@ def shell(cbs, orc):
 
 
 @pytest.mark.timeout(400)
-def test_shell256_fp64_iterates_sampled(cbs, shell):
+def test_shell256_fp64_iterates_sampled(cbs, shell, report):
     pr, gm, om = shell
+    report("shell3d 256^3: oracle 2 FP64 iterations")
     sp = pr.dense_source()
     so, sg = om.scalars(), gm.scalars()
     for k in ("a1", "a2", "lam1", "lam2"):
@@ -72,23 +74,36 @@ def test_shell256_fp64_iterates_sampled(cbs, shell):
         assert _rel(p[sl], xi[-1][sl]) <= 1e-10
 
 
-@pytest.mark.timeout(600)
-def test_shell256_refined_accuracy(cbs, shell):
+@pytest.mark.timeout(900)
+def test_shell256_refined_accuracy(cbs, shell, report):
+    """The skull-like case is ill-conditioned: the error is ~40x the scaled
+    residual, for FP64 and refined FP32 alike.  A 1e-5 error therefore needs a
+    residual of ~1e-7; both paths are solved to 1e-7 and compared with the
+    FP64 solution at 1e-10 (itself iterate-pinned to the oracle above)."""
     import torch
     from paper_2507_16087_amd import _lib
     pr, gm, om = shell
     sp = torch.from_numpy(pr.dense_source().ravel()).cuda()
-    p32, u32, i32 = cbs.solve(gm, sp, tol=1e-6, prec="fp32_refined", max_iter=200000,
+    report("shell3d 256^3: refined FP32 solve to 1e-7")
+    p32, u32, i32 = cbs.solve(gm, sp, tol=1e-7, prec="fp32_refined", max_iter=400000,
                               check_every=50)
-    assert i32["converged"] and i32["rel_residual"] <= 1e-6
+    report(f"  {i32['iterations']} iterations; oracle residual of the result")
+    assert i32["converged"] and i32["rel_residual"] <= 1e-7
     # the oracle's operator agrees with the GPU-reported residual
     xi = np.concatenate([u32.cpu().numpy(), p32.cpu().numpy()[None]])
     shat = om.source_hat(om.pressure_source(pr.dense_source()))
     r_orc = om.rel_residual(shat, xi)
-    del shat, xi
+    del shat, xi, u32
     assert abs(r_orc - i32["rel_residual"]) <= 1e-3 * i32["rel_residual"] + 1e-12
-    p64, _, i64 = cbs.solve(gm, sp, tol=1e-9, prec="fp64", max_iter=200000, check_every=100,
+    report("shell3d 256^3: FP64 reference solve to 1e-10")
+    ref, _, iref = cbs.solve(gm, sp, tol=1e-10, prec="fp64", max_iter=400000, check_every=200,
+                             stop_rule=_lib.CBS_STOP_RESIDUAL, want_u=False)
+    report(f"  {iref['iterations']} iterations; FP64 solve to 1e-7")
+    assert iref["converged"]
+    p64, _, i64 = cbs.solve(gm, sp, tol=1e-7, prec="fp64", max_iter=400000, check_every=50,
                             stop_rule=_lib.CBS_STOP_RESIDUAL, want_u=False)
-    assert i64["converged"]
-    err = (torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)).item()
-    assert err <= 1e-5, err
+    e32 = (torch.linalg.norm(p32 - ref) / torch.linalg.norm(ref)).item()
+    e64 = (torch.linalg.norm(p64 - ref) / torch.linalg.norm(ref)).item()
+    print(f"256^3 shell at residual 1e-7: refined FP32 error {e32:.2e} "
+          f"({i32['iterations']} it), FP64 error {e64:.2e} ({i64['iterations']} it)")
+    assert e32 <= 1e-5, (e32, e64)

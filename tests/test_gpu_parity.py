@@ -133,3 +133,67 @@ def test_gradient_kernel_matches_oracle(orc, cbs, shape):
     gg = cbs.gradient(gm, s[-1], s[:-1], xi[-1], xi[:-1], lam[-1], lam[:-1])
     for a, b in zip(gg, go):
         assert _rel(a, b) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(24, 32), (12, 192), (16, 24, 32), (8, 96, 12)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_collocated_iterates_match_oracle(orc, cbs, shape, adjoint):
+    """Collocated-grid variant (App. B first matrix): same kernels, planner
+    tables without the half-cell shift and with the Nyquist derivative bin
+    zeroed; the oracle applies the collocated matrix explicitly."""
+    c, rho, alpha = W.small_random(shape, 3)
+    om = orc.OracleMedium(shape, DX, OMEGA, c, rho, alpha, pml=2, collocated=True)
+    gm = cbs.Medium(shape, DX, OMEGA, c, rho, alpha, pml=2, collocated=True)
+    so, sg = om.scalars(), gm.scalars()
+    assert abs(so["a1"] - sg["a1"]) <= 1e-12 * abs(so["a1"])
+    F = len(shape) + 1
+    s = np.zeros((F,) + shape, complex)
+    flat = s.reshape(F, -1)
+    flat[-1, [5, 77]] = [1.0, 0.5j]
+    flat[0, 13] = 0.2
+    xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=40, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=0.0, max_iter=40, adjoint=adjoint)
+    assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
+
+
+def test_collocated_gradient_kernel(orc, cbs):
+    shape = (12, 16, 8)
+    c, rho, alpha = W.small_random(shape, 9)
+    om = orc.OracleMedium(shape, DX, OMEGA, c, rho, alpha, pml=2, collocated=True)
+    gm = cbs.Medium(shape, DX, OMEGA, c, rho, alpha, pml=2, collocated=True)
+    rng = np.random.default_rng(1)
+    rc = [rng.standard_normal((4,) + shape) + 1j * rng.standard_normal((4,) + shape) for _ in range(3)]
+    go = om.gradient(*rc)
+    gg = cbs.gradient(gm, rc[0][-1], rc[0][:-1], rc[1][-1], rc[1][:-1], rc[2][-1], rc[2][:-1])
+    for a, b in zip(gg, go):
+        assert _rel(a, b) <= 1e-12
+
+
+def _prop_plan(gm, prec):
+    return next(p for p in gm.pass_config(prec) if p["kind"] == 4)
+
+
+@pytest.mark.parametrize("variant", ["0", "1"])
+@pytest.mark.parametrize("shape", [(48, 32), (16, 24, 32), (64, 8, 16), (256, 4, 8)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_propagator_variants_match_oracle(orc, cbs, monkeypatch, variant, shape, adjoint):
+    """Both propagator-pass variants (one LDS region reused per field, or one
+    region per field sharing each exchange) against the oracle, FP64 iterates
+    and the refined FP32 solve."""
+    monkeypatch.setenv("CBS_PROP_VARIANT", variant)
+    om, gm = _pair(orc, cbs, shape, pml=1, seed=5)
+    F = len(shape) + 1
+    s = np.zeros((F,) + shape, complex)
+    flat = s.reshape(F, -1)
+    flat[-1, [3, 401]] = [1.0, -0.4j]
+    flat[1, 77] = 0.25
+    xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=25, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=0.0, max_iter=25, adjoint=adjoint)
+    assert _prop_plan(gm, "fp64")["shared_lds"] == (variant == "1")
+    assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
+    xs, _ = om.solve(om.source_hat(s), tol=1e-12, max_iter=100000, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=1e-7, prec="fp32_refined", inner_tol=1e-4,
+                           adjoint=adjoint)
+    assert info["converged"]
+    assert _prop_plan(gm, "fp32_refined")["shared_lds"] == (variant == "1")
+    assert _rel(p, xs[-1]) <= 1e-5 and _rel(u, xs[:-1]) <= 1e-5
