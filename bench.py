@@ -41,8 +41,14 @@ PASS_NAMES = ["fwd_axis2_prologue", "fwd_axis1", "axis0_propagator", "inv_axis1"
 PASS_BYTES_F32 = [116, 64, 64, 64, 180]
 
 
-KERNEL_FOR_PASS = {"inv_axis2_update_fwd_axis2": "k_lastaxis", "axis0_propagator": "k_prop",
-                   "fwd_axis1": "k_strided", "inv_axis1": "k_strided"}
+def _kernel_suffix(pass_name, plan):
+    """Trailing template arguments that name this pass's kernel instance in a
+    rocprofv3 summary (mode, kind / direction, variant, precision)."""
+    v = plan.get("variant", 0) if plan else 0
+    return {"inv_axis2_update_fwd_axis2": ("k_lastaxis", f", 0, 2, {v}, float>"),
+            "axis0_propagator": ("k_prop", f", 0, {v}, float>"),
+            "fwd_axis1": ("k_strided", ", -1, float>"),
+            "inv_axis1": ("k_strided", ", 1, float>")}.get(pass_name)
 
 
 def committed_traffic(pass_name, plan):
@@ -57,18 +63,15 @@ def committed_traffic(pass_name, plan):
     text = open(prof).read()
     if f"sha256[:16]: {cur}" not in text:
         return None
-    want = KERNEL_FOR_PASS.get(pass_name)
+    want = _kernel_suffix(pass_name, plan)
+    if want is None:
+        return None
     tpl = f"Plan<{plan['n']}, " if plan else ""
     for line in text.splitlines():
-        if line.startswith("#") or not line.startswith(want or "?"):
+        if line.startswith("#") or not line.startswith(want[0] + "<" + tpl):
             continue
-        parts = line.split()
-        if "float>" in line and tpl in line:
-            if pass_name == "inv_axis1" and ", 1, float>" not in line:
-                continue
-            if pass_name == "fwd_axis1" and ", -1, float>" not in line:
-                continue
-            return float(parts[-2])
+        if want[1] in line:
+            return float(line.split()[-2])
     return None
 
 

@@ -76,7 +76,8 @@ struct Pass {
     int n;
     int pcols;
     bool wide;
-    int variant;   // propagator: 1 = all fields' FFT stages share each LDS exchange
+    int variant;   // propagator: LDS regions (0 one, 1 per field, 2 two);
+                   // last-axis inverse: prefetch (0 none, 1 x y medium, 2 x medium)
 };
 
 struct PassSet {
@@ -438,24 +439,26 @@ hipError_t run_passes(cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T
 // every medium of one shape runs the same kernels (results of a solve do not
 // depend on which other solves ran first).  CBS_AUTOTUNE=0 keeps the defaults.
 struct TuneKey {
-    int ndim, n0, n1, n2, fp64, prop_variant;
+    int ndim, n0, n1, n2, fp64, prop_variant, last_variant;
     bool operator<(const TuneKey& o) const {
-        return std::tie(ndim, n0, n1, n2, fp64, prop_variant) <
-               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant);
+        return std::tie(ndim, n0, n1, n2, fp64, prop_variant, last_variant) <
+               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant, o.last_variant);
     }
 };
 
-// CBS_PROP_VARIANT=0 or 1 pins the propagator pass to one variant (per-field
-// LDS exchanges, or all fields sharing each exchange); unset, both compete.
-int forced_prop_variant() {
-    const char* e = std::getenv("CBS_PROP_VARIANT");
-    if (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) return e[0] - '0';
+// CBS_PROP_VARIANT=0, 1 or 2 pins the propagator pass to one LDS variant
+// (one tile reused field by field; one region per field; two regions, fields
+// in pairs) and CBS_LAST_VARIANT=0, 1 or 2 the last-axis inverse pass to one
+// prefetch variant (none; x, y and medium; x and medium); unset, all compete.
+int forced_variant(int kind) {
+    const char* e = std::getenv(kind == 4 ? "CBS_PROP_VARIANT" : "CBS_LAST_VARIANT");
+    if (e && e[0] >= '0' && e[0] <= '2' && e[1] == 0) return e[0] - '0';
     return -1;
 }
 std::mutex g_tune_mu;
 std::map<TuneKey, PassSet> g_tune_cache;
 
-std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64, int prop_variant) {
+std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
     std::vector<Pass> out;
     const int last = g.ndim - 1;
     const bool lastaxis = base.kind == 0 || base.kind == 1;
@@ -478,8 +481,11 @@ std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64, in
             Pass p = base;
             p.wide = wide != 0;
             p.pcols = pc;
-            for (int v = 0; v < (base.kind == 4 ? 2 : 1); ++v) {
-                if (base.kind == 4 && prop_variant >= 0 && v != prop_variant) continue;
+            // propagator: LDS variants; last-axis inverse: prefetch variants
+            const bool has_var = base.kind == 4 || base.kind == 1;
+            const int pinned = has_var ? forced_variant(base.kind) : -1;
+            for (int v = 0; v < (has_var ? 3 : 1); ++v) {
+                if (pinned >= 0 && v != pinned) continue;
                 p.variant = v;
                 out.push_back(p);
             }
@@ -530,7 +536,7 @@ cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T
         const int kind = (i == ps.count - 1) ? 5 : ps.p[i].kind;
         float best = -1.f;
         Pass pick = ps.p[i];
-        for (const Pass& c : pass_candidates(m->g, ps.p[i], fp64, forced_prop_variant())) {
+        for (const Pass& c : pass_candidates(m->g, ps.p[i], fp64)) {
             const float t = time_pass<T>(m, kind, dslot, c, st);
             if (t > 0.f && (best < 0.f || t < best)) {
                 best = t;
@@ -599,10 +605,10 @@ bool autotune_enabled() {
 // contents are scratch here), or take them from the process cache.
 cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
     if (!autotune_enabled()) {
-        const int v = forced_prop_variant();
         for (PassSet* ps : {&m->ps64, &m->ps32})
             for (int i = 0; i < ps->count; ++i)
-                if (ps->p[i].kind == 4) ps->p[i].variant = v > 0 ? v : 0;
+                if (ps->p[i].kind == 4 || ps->p[i].kind == 1)
+                    ps->p[i].variant = std::max(0, forced_variant(ps->p[i].kind));
         return CBS_OK;
     }
     const Layout L = layout_for(m, prec);
@@ -612,7 +618,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         bool& done = fp64 ? m->tuned64 : m->tuned32;
         if (done) continue;
         PassSet& ps = fp64 ? m->ps64 : m->ps32;
-        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_prop_variant()};
+        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_variant(4), forced_variant(1)};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(key);

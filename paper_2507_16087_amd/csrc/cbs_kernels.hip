@@ -437,7 +437,10 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 //                elements the forward transform's first stage needs.
 enum Kind { FIRST = 0, LAST = 1, FUSED = 2 };
 
-template <class P, int MODE, int KIND, typename T>
+//   PF (LAST / FUSED): 0 loads x, y and the medium after the inverse
+//   transform; 1 issues all three right after the w loads, so they travel
+//   while the transform runs; 2 prefetches x and the medium only.
+template <class P, int MODE, int KIND, int PF, typename T>
 __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ slots, Geom g, int pcols) {
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -490,17 +493,20 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
     const T aim = s.adjoint ? -(urow ? s.a1im : s.a2im) : (urow ? s.a1im : s.a2im);
     const T il = urow ? s.inv_lam1 : s.inv_lam2;
     const T wim = s.adjoint ? -s.omega : s.omega;
-    // diagonal D (conjugated for the adjoint) at element n of the pencil
-    auto diag = [&](int n) -> cx<T> {
+    // medium value at element n: rhobar (real part) on velocity rows, q on
+    // the pressure row
+    auto medium = [&](int n) -> cx<T> {
+        if (urow) return {rb[n], T(0)};
+        return qv[n];
+    };
+    // diagonal D (conjugated for the adjoint) at element n from its medium value
+    auto diag_m = [&](int n, cx<T> m) -> cx<T> {
         const T gam = s.gmax * (colsum + lastprof[n]);
-        if (urow) {
-            const T r = rb[n];
-            return {r * gam, r * wim};
-        }
-        const cx<T> q = qv[n];
-        const cx<T> dd = {gam * q.re - s.omega * q.im, gam * q.im + s.omega * q.re};
+        if (urow) return {m.re * gam, m.re * wim};
+        const cx<T> dd = {gam * m.re - s.omega * m.im, gam * m.im + s.omega * m.re};
         return {dd.re, s.adjoint ? -dd.im : dd.im};
     };
+    auto diag = [&](int n) -> cx<T> { return diag_m(n, medium(n)); };
 
     cx<T> v[E];
     using QF = Seq<P, -1>;
@@ -527,9 +533,22 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
         for (int b = 0; b < N / (R0 * TPC); ++b)
 #pragma unroll
             for (int r = 0; r < R0; ++r) v[b * R0 + r] = w[pl + in_index<P, 1>(lane, b, r)];
+        constexpr int RL = QI::r(P::S - 1);   // == forward R0
+        constexpr int EP = PF ? E : 1, EY = PF == 1 ? E : 1;
+        cx<T> xp[EP], mp[EP], yp[EY];
+        if constexpr (PF != 0) {
+#pragma unroll
+            for (int b = 0; b < N / (RL * TPC); ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int n = out_index<P, 1>(lane, b, r);
+                    xp[b * RL + r] = x[pl + n];
+                    mp[b * RL + r] = medium(n);
+                    if constexpr (PF == 1) yp[b * RL + r] = y[pl + n];
+                }
+        }
         fft_regs<P, 1, ROWS>(v, lds, ldp, col, lane, tw);
         double acc0 = 0.0, acc1 = 0.0;
-        constexpr int RL = QI::r(P::S - 1);   // == forward R0
 #pragma unroll
         for (int b = 0; b < N / (RL * TPC); ++b)
 #pragma unroll
@@ -537,8 +556,8 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                 const int n = out_index<P, 1>(lane, b, r);
                 const int e = b * RL + r;
                 const cx<T> z = v[e];
-                const cx<T> xv = x[pl + n];
-                const cx<T> dd = diag(n);
+                const cx<T> xv = PF ? xp[PF ? e : 0] : x[pl + n];
+                const cx<T> dd = PF ? diag_m(n, mp[PF ? e : 0]) : diag(n);
                 if constexpr (MODE == CBS) {
                     const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
                     const cx<T> dxv = rmul(s.nu, cmul(bb, z - xv));
@@ -546,9 +565,9 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                     x[pl + n] = xn;
                     acc0 += (double)norm2(dxv);
                     acc1 += (double)norm2(xv);
-                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + y[pl + n];
+                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : y[pl + n]);
                 } else {
-                    const cx<T> yv = y[pl + n];
+                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : y[pl + n];
                     const cx<T> rr = yv - rmul(il, cmul(dd, xv)) - z;
                     w[pl + n] = rr;
                     acc0 += (double)norm2(rr);
@@ -631,9 +650,12 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 // FFT.  MODE CBS applies (L+I)^{-1} of App. B.1 (rank-one form, conjugate
 // transpose for the adjoint); MODE APPLY applies the scaled staggered
 // derivative block of L (negated for the adjoint).  1/prod(n) is folded in.
-template <class P, int MODE, bool MULTI, typename T>
-__global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols,
-                                              int ldp, int64_t es, int64_t ostride, int nlast_tiles, int xg) {
+template <class P, int MODE, int VAR, typename T>
+__global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols, int ldp,
+                                              int64_t es, int64_t ostride, int nlast_tiles, int xg) {
+    // VAR 0: one LDS tile, fields in turn; 1: one region per field, every
+    // exchange shared by all fields; 2: two regions, fields in pairs.
+    constexpr int NR = VAR == 1 ? 4 : (VAR == 2 ? 2 : 1);
     extern __shared__ unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
@@ -647,9 +669,9 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     const int il = (tile % nlast_tiles) * pcols + col;              // index along the last axis
     cx<T>* __restrict__ wt = s.w + (int64_t)io * ostride + (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
-    // LDS: tile (one per field when MULTI) | twiddles (N) | k0 S0 (N) | k0 (N)
+    // LDS: NR field tiles | twiddles (N) | k0 S0 (N) | k0 (N)
     const int field_elems = (int)(tile_bytes<T>((size_t)N * ldp) / sizeof(cx<T>));
-    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + (size_t)(MULTI ? 4 : 1) * field_elems * sizeof(cx<T>));
+    cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + (size_t)NR * field_elems * sizeof(cx<T>));
     cx<T>* g0_l = tw_l + N;
     T* k0_l = reinterpret_cast<T*>(g0_l + N);
     for (int i = tid; i < N; i += blockDim.x) {
@@ -690,8 +712,12 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
                     v[f][b * R0 + r] = wf[(uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32];
         }
     }
-    if constexpr (MULTI) {
+    if constexpr (NR == 4) {
         fft_regs_multi<P, -1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+    } else if constexpr (NR == 2) {
+        fft_regs_multi<P, -1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
+        __syncthreads();
+        fft_regs_multi<P, -1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
     } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -754,14 +780,19 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     // inverse FFT from the registers and store
     using QI = Seq<P, 1>;
     constexpr int RL = QI::r(P::S - 1);
-    if constexpr (MULTI) {
+    if constexpr (NR == 4) {
         __syncthreads();
         fft_regs_multi<P, 1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+    } else if constexpr (NR == 2) {
+        __syncthreads();
+        fft_regs_multi<P, 1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
+        __syncthreads();
+        fft_regs_multi<P, 1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         if (f < F) {
-            if constexpr (!MULTI) {
+            if constexpr (NR == 1) {
                 __syncthreads();
                 fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
             }
@@ -1060,19 +1091,26 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         const size_t lr = std::max(tile_bytes<T>((size_t)pcols * lds_pitch<ROWS>(N, 0)), (size_t)(64 * sizeof(double))) +
                           (size_t)N * (sizeof(cx<T>) + sizeof(T));
         if (lr > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+#define LA_LAUNCH(M, K, PF_) hipLaunchKernelGGL((k_lastaxis<P, M, K, PF_, T>), grid, blk, lr, st, slots, g, pcols)
         if (kind == 0) {
-            if (mode == CBS)
-                hipLaunchKernelGGL((k_lastaxis<P, CBS, FIRST, T>), grid, blk, lr, st, slots, g, pcols);
-            else
-                hipLaunchKernelGGL((k_lastaxis<P, APPLY, FIRST, T>), grid, blk, lr, st, slots, g, pcols);
+            if (mode == CBS) LA_LAUNCH(CBS, FIRST, 0);
+            else LA_LAUNCH(APPLY, FIRST, 0);
         } else if (kind == 1) {
-            if (mode == CBS)
-                hipLaunchKernelGGL((k_lastaxis<P, CBS, LAST, T>), grid, blk, lr, st, slots, g, pcols);
-            else
-                hipLaunchKernelGGL((k_lastaxis<P, APPLY, LAST, T>), grid, blk, lr, st, slots, g, pcols);
+            if (mode == CBS) {
+                if (variant == 1) LA_LAUNCH(CBS, LAST, 1);
+                else if (variant == 2) LA_LAUNCH(CBS, LAST, 2);
+                else LA_LAUNCH(CBS, LAST, 0);
+            } else {
+                if (variant == 1) LA_LAUNCH(APPLY, LAST, 1);
+                else if (variant == 2) LA_LAUNCH(APPLY, LAST, 2);
+                else LA_LAUNCH(APPLY, LAST, 0);
+            }
         } else {
-            hipLaunchKernelGGL((k_lastaxis<P, CBS, FUSED, T>), grid, blk, lr, st, slots, g, pcols);
+            if (variant == 1) LA_LAUNCH(CBS, FUSED, 1);
+            else if (variant == 2) LA_LAUNCH(CBS, FUSED, 2);
+            else LA_LAUNCH(CBS, FUSED, 0);
         }
+#undef LA_LAUNCH
     } else {
         // strided along `axis`; columns run along the last axis in groups of pcols
         int64_t es = 1;
@@ -1095,21 +1133,22 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         if (xg < 1 || nlast_tiles % xg) xg = 1;
         if (kind == 4) {
             const dim3 grid(tiles, 1, nslots);
-            const bool multi = variant == 1;
-            const size_t lp = multi ? lds + 3 * tile_bytes<T>((size_t)N * ldp) : lds;
+            const int nr = variant == 1 ? 4 : (variant == 2 ? 2 : 1);
+            const size_t lp = lds + (size_t)(nr - 1) * tile_bytes<T>((size_t)N * ldp);
             if (lp > kMaxLdsBytes) return hipErrorInvalidConfiguration;
-            if (mode == CBS && multi)
-                hipLaunchKernelGGL((k_prop<P, CBS, true, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
-                                   ostride, nlast_tiles, xg);
-            else if (mode == CBS)
-                hipLaunchKernelGGL((k_prop<P, CBS, false, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
-                                   ostride, nlast_tiles, xg);
-            else if (multi)
-                hipLaunchKernelGGL((k_prop<P, APPLY, true, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
-                                   ostride, nlast_tiles, xg);
-            else
-                hipLaunchKernelGGL((k_prop<P, APPLY, false, T>), grid, block, lp, st, slots, g, pcols, ldp, es,
-                                   ostride, nlast_tiles, xg);
+#define PROP_LAUNCH(M, V)                                                                                     \
+    hipLaunchKernelGGL((k_prop<P, M, V, T>), grid, block, lp, st, slots, g, pcols, ldp, es, ostride, nlast_tiles, \
+                       xg)
+            if (mode == CBS) {
+                if (variant == 1) PROP_LAUNCH(CBS, 1);
+                else if (variant == 2) PROP_LAUNCH(CBS, 2);
+                else PROP_LAUNCH(CBS, 0);
+            } else {
+                if (variant == 1) PROP_LAUNCH(APPLY, 1);
+                else if (variant == 2) PROP_LAUNCH(APPLY, 2);
+                else PROP_LAUNCH(APPLY, 0);
+            }
+#undef PROP_LAUNCH
         } else {
             if (lds > kMaxLdsBytes) return hipErrorInvalidConfiguration;
             const dim3 grid(tiles, F, nslots);

@@ -169,18 +169,22 @@ def test_collocated_gradient_kernel(orc, cbs):
         assert _rel(a, b) <= 1e-12
 
 
-def _prop_plan(gm, prec):
-    return next(p for p in gm.pass_config(prec) if p["kind"] == 4)
+def _plan(gm, prec, kind):
+    return next(p for p in gm.pass_config(prec) if p["kind"] == kind)
 
 
-@pytest.mark.parametrize("variant", ["0", "1"])
+@pytest.mark.parametrize("pin", [("CBS_PROP_VARIANT", 0), ("CBS_PROP_VARIANT", 1), ("CBS_PROP_VARIANT", 2),
+                                 ("CBS_LAST_VARIANT", 1), ("CBS_LAST_VARIANT", 2)])
 @pytest.mark.parametrize("shape", [(48, 32), (16, 24, 32), (64, 8, 16), (256, 4, 8)])
 @pytest.mark.parametrize("adjoint", [False, True])
-def test_propagator_variants_match_oracle(orc, cbs, monkeypatch, variant, shape, adjoint):
-    """Both propagator-pass variants (one LDS region reused per field, or one
-    region per field sharing each exchange) against the oracle, FP64 iterates
-    and the refined FP32 solve."""
-    monkeypatch.setenv("CBS_PROP_VARIANT", variant)
+def test_pass_variants_match_oracle(orc, cbs, monkeypatch, pin, shape, adjoint):
+    """Every pass variant the tuner may pick, pinned in turn, against the
+    oracle: the propagator's LDS layouts (one tile reused field by field, one
+    region per field, fields in pairs) and the last-axis inverse pass's
+    prefetch of x, y and the medium.  FP64 iterates and the refined FP32 solve."""
+    name, variant = pin
+    monkeypatch.setenv(name, str(variant))
+    kind = 4 if name == "CBS_PROP_VARIANT" else 1
     om, gm = _pair(orc, cbs, shape, pml=1, seed=5)
     F = len(shape) + 1
     s = np.zeros((F,) + shape, complex)
@@ -189,11 +193,11 @@ def test_propagator_variants_match_oracle(orc, cbs, monkeypatch, variant, shape,
     flat[1, 77] = 0.25
     xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=25, adjoint=adjoint)
     p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=0.0, max_iter=25, adjoint=adjoint)
-    assert _prop_plan(gm, "fp64")["shared_lds"] == (variant == "1")
+    assert _plan(gm, "fp64", kind)["variant"] == variant
     assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
     xs, _ = om.solve(om.source_hat(s), tol=1e-12, max_iter=100000, adjoint=adjoint)
     p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=1e-7, prec="fp32_refined", inner_tol=1e-4,
                            adjoint=adjoint)
     assert info["converged"]
-    assert _prop_plan(gm, "fp32_refined")["shared_lds"] == (variant == "1")
+    assert _plan(gm, "fp32_refined", kind)["variant"] == variant
     assert _rel(p, xs[-1]) <= 1e-5 and _rel(u, xs[:-1]) <= 1e-5
