@@ -16,7 +16,7 @@
  * Conventions shared by every entry point
  *  - Grid: ndim in {2, 3}; n[eta] cells per axis, C order, last axis
  *    contiguous.  Each n[eta] must be one of 4, 6, 8, 12, 16, 24, 32, 48, 64,
- *    96, 128, 192, 256 (else CBS_E_UNSUPPORTED).  Cell centres sit at integer
+ *    96, 128, 192, 256, 512 (else CBS_E_UNSUPPORTED).  Cell centres sit at integer
  *    multiples of dx; u_eta sits half a cell further along eta.
  *  - Units: SI.  alpha in Np/m, omega in rad/s.
  *  - Media c, rho, alpha: real float64 arrays of prod(n) cells.  c > 0,
@@ -199,17 +199,23 @@ cbs_status cbs_gradient(cbs_medium m, const void *s_p, const void *s_u, const vo
  * host synchronisation; enable = 0 stops recording. */
 cbs_status cbs_pass_timing(cbs_medium m, int32_t enable);
 
+/* Which pass slots cbs_pass_timing brackets with events: bit k set = slot k
+ * (the slots of cbs_pass_timing_read; default 0x3f, all six).  Every event
+ * pair adds a few microseconds between kernels, so a measurement of one pass
+ * can leave the others unbracketed.  CBS_E_INVALID outside [0, 0x3f]. */
+cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
+
 /* Pass plans in use for precision prec (after the first solve tunes them):
  * out[4 i + 0..3] = kind, axis length, columns per work-group, flags of pass i
  * (kind -1 = unused; flag bit 0 = wide radix split, bits 1-2 = variant: for
  * the propagator pass the LDS layout -- 0 one tile reused field by field, 1
  * one region per field with every exchange shared, 2 two regions with fields
- * in pairs; for the last-axis inverse pass the prefetch -- 0 none, 1 x, y and
- * the medium issued before the transform, 2 x and the medium).  The first
- * solve of each (shape, precision) in a process times the candidate plans on
- * its workspace and keeps the fastest (set CBS_AUTOTUNE=0 in the environment
- * to keep the defaults; CBS_PROP_VARIANT and CBS_LAST_VARIANT = 0, 1 or 2 pin
- * the two variants, tuned or not).
+ * in pairs; for the last-axis inverse pass the prefetch -- 0 none, 1 x, y
+ * and the medium issued before the transform, 2 x and the medium).  The
+ * first solve of each (shape, precision) in a process times the candidate
+ * plans on its workspace and keeps the fastest (set CBS_AUTOTUNE=0 in the
+ * environment to keep the defaults; CBS_PROP_VARIANT and CBS_LAST_VARIANT =
+ * 0, 1 or 2 pin the two variants, tuned or not).
  * Configurations needing more than 160 KiB of LDS are never launched. */
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
 

@@ -34,7 +34,7 @@ CBS_STOP_RESIDUAL = 1
 EXPORTS = [
     "cbs_create_medium", "cbs_destroy_medium", "cbs_medium_scalars", "cbs_set_scalars",
     "cbs_workspace_bytes", "cbs_solve", "cbs_solve_adjoint", "cbs_residual", "cbs_gradient",
-    "cbs_pass_config", "cbs_pass_timing", "cbs_pass_timing_read",
+    "cbs_pass_config", "cbs_pass_timing", "cbs_pass_timing_slots", "cbs_pass_timing_read",
     "cbs_batch_workspace_bytes", "cbs_batch_create", "cbs_batch_destroy", "cbs_batch_submit",
     "cbs_batch_step", "cbs_batch_retire",
 ]
@@ -86,6 +86,7 @@ def lib() -> C.CDLL:
     L.cbs_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
     L.cbs_pass_config.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.cbs_pass_timing.argtypes = [vp, i32]
+    L.cbs_pass_timing_slots.argtypes = [vp, i32]
     L.cbs_pass_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
     L.cbs_batch_workspace_bytes.argtypes = [C.POINTER(Grid), i32, i32, C.POINTER(C.c_size_t)]
     L.cbs_batch_create.argtypes = [C.POINTER(Grid), i32, i32, vp, C.c_size_t, vp, C.POINTER(vp)]

@@ -59,7 +59,7 @@ using namespace cbs;
 
 namespace {
 
-const int kSizes[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+const int kSizes[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512};
 
 bool size_supported(int64_t n) {
     for (int s : kSizes)
@@ -252,6 +252,7 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // CBS, 2 FP64 residual; slots 0..4 = passes in launch order, 5 = reduction.
 struct PassTiming {
     bool on = false;
+    int mask = 0x3f;   // pass slots bracketed with events (bit k = slot k)
     std::vector<hipEvent_t> ev;
     std::vector<int> tag;
     size_t used = 0;
@@ -341,6 +342,7 @@ Slot<T> make_slot(const cbs_medium_s* m, cx<T>* x, cx<T>* w, const cx<T>* y, Ctl
     s.al1 = tocx<T>(al1);
     s.al2 = tocx<T>(al2);
     s.ca = tocx<T>(m->lam1 / al1);
+    s.can = tocx<T>(m->lam1 / al1 / (double)m->g.ncell);
     s.cp = tocx<T>(m->lam2 * al1);
     s.al12 = tocx<T>(al1 * al2);
     s.adjoint = adjoint;
@@ -411,17 +413,19 @@ hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int 
         const bool pro = mode == MODE_CBS && i == 0;
         if (pro && nstart == 0) continue;
         const int kind = (mode == MODE_CBS && i == ps.count - 1) ? 5 : p.kind;
-        if (timed && timing_begin(*tp, group * 8 + (i == ps.count - 1 ? 4 : i), st) != hipSuccess)
-            return hipErrorUnknown;
+        const int slot = i == ps.count - 1 ? 4 : i;
+        const bool ev = timed && ((tp->mask >> slot) & 1);
+        if (ev && timing_begin(*tp, group * 8 + slot, st) != hipSuccess) return hipErrorUnknown;
         hipError_t e = launch_pass<T>(kind, mode, pro ? starts : all, pro ? nstart : nall, g, p.axis, p.n, p.pcols,
                                       p.wide, p.variant, st);
         if (e != hipSuccess) return e;
-        if (timed && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
+        if (ev && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
     }
-    if (timed && timing_begin(*tp, group * 8 + 5, st) != hipSuccess) return hipErrorUnknown;
+    const bool ev = timed && ((tp->mask >> 5) & 1);
+    if (ev && timing_begin(*tp, group * 8 + 5, st) != hipSuccess) return hipErrorUnknown;
     hipError_t e = launch_reduce<T>(mode == MODE_CBS, all, ps.nparts, nall, st);
     if (e != hipSuccess) return e;
-    if (timed && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
+    if (ev && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
     return hipSuccess;
 }
 
@@ -446,13 +450,23 @@ struct TuneKey {
     }
 };
 
-// CBS_PROP_VARIANT=0, 1 or 2 pins the propagator pass to one LDS variant
-// (one tile reused field by field; one region per field; two regions, fields
-// in pairs) and CBS_LAST_VARIANT=0, 1 or 2 the last-axis inverse pass to one
-// prefetch variant (none; x, y and medium; x and medium); unset, all compete.
+// Variants a pass kind may take: the propagator's LDS layouts (0 one tile
+// reused field by field, 1 one region per field, 2 two regions with fields in
+// pairs); the last-axis inverse pass's prefetch (0 none, 1 x, y and medium,
+// 2 x and medium).
+std::vector<int> variants_of(int kind) {
+    if (kind == 4 || kind == 1) return {0, 1, 2};
+    return {0};
+}
+
+// CBS_PROP_VARIANT pins the propagator pass and CBS_LAST_VARIANT the
+// last-axis inverse pass to one of their variants; unset, all compete.
 int forced_variant(int kind) {
     const char* e = std::getenv(kind == 4 ? "CBS_PROP_VARIANT" : "CBS_LAST_VARIANT");
-    if (e && e[0] >= '0' && e[0] <= '2' && e[1] == 0) return e[0] - '0';
+    if (!e || e[0] < '0' || e[0] > '9' || e[1] != 0) return -1;
+    const int v = e[0] - '0';
+    for (int ok : variants_of(kind))
+        if (ok == v) return v;
     return -1;
 }
 std::mutex g_tune_mu;
@@ -481,10 +495,8 @@ std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
             Pass p = base;
             p.wide = wide != 0;
             p.pcols = pc;
-            // propagator: LDS variants; last-axis inverse: prefetch variants
-            const bool has_var = base.kind == 4 || base.kind == 1;
-            const int pinned = has_var ? forced_variant(base.kind) : -1;
-            for (int v = 0; v < (has_var ? 3 : 1); ++v) {
+            const int pinned = forced_variant(base.kind);
+            for (int v : variants_of(base.kind)) {
                 if (pinned >= 0 && v != pinned) continue;
                 p.variant = v;
                 out.push_back(p);
@@ -503,15 +515,15 @@ float time_pass(cbs_medium_s* m, int kind, const Slot<T>* dslot, const Pass& p, 
         return -1.f;
     }
     float ms = -1.f;
+    auto once = [&]() {
+        return launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, p.variant, st) ==
+               hipSuccess;
+    };
     bool ok = true;
-    for (int i = 0; i < 2 && ok; ++i)
-        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, p.variant, st) ==
-             hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i) ok = once();
     const int reps = 6;
     ok = ok && hipEventRecord(a, st) == hipSuccess;
-    for (int i = 0; i < reps && ok; ++i)
-        ok = launch_pass<T>(kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, p.variant, st) ==
-             hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = once();
     ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
     if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms /= reps;
     else ms = -1.f;
@@ -522,13 +534,14 @@ float time_pass(cbs_medium_s* m, int kind, const Slot<T>* dslot, const Pass& p, 
 
 template <typename T>
 cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T>* w, cx<T>* y, Ctl* ctl,
-                    double* part, hipStream_t st) {
+                    double* part, double* chunks, hipStream_t st) {
     const int64_t nf = (int64_t)(m->g.ndim + 1) * m->g.ncell;
     HIPOK(launch_zero<T>(x, nf, st));
     HIPOK(launch_zero<T>(w, nf, st));
     HIPOK(launch_zero<T>(y, nf, st));
     HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
-    Slot<T> h = make_slot<T>(m, x, w, y, ctl, part, 0, nullptr);
+    HIPOK(launch_ctl_reset(ctl, INT32_MAX, -1.0, st));   // candidates never see a finished slot
+    Slot<T> h = make_slot<T>(m, x, w, y, ctl, part, 0, chunks);
     HIPOK(hipMemcpyAsync(dslot, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIPOK(hipStreamSynchronize(st));
     const bool fp64 = sizeof(T) == 8;
@@ -632,11 +645,13 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         if (fp64)
             cs = tune_set<double>(m, ps, at<Slot<double>>(ws, L.off_slot64), at<cx<double>>(ws, L.off_x64),
                                   at<cx<double>>(ws, L.off_w64), at<cx<double>>(ws, L.off_y64),
-                                  at<Ctl>(ws, L.off_ctl64), at<double>(ws, L.off_part64), st);
+                                  at<Ctl>(ws, L.off_ctl64), at<double>(ws, L.off_part64),
+                                  at<double>(ws, L.off_chunk64), st);
         else
             cs = tune_set<float>(m, ps, at<Slot<float>>(ws, L.off_slot32), at<cx<float>>(ws, L.off_d32),
                                  at<cx<float>>(ws, L.off_w32), at<cx<float>>(ws, L.off_y32),
-                                 at<Ctl>(ws, L.off_ctl32), at<double>(ws, L.off_part32), st);
+                                 at<Ctl>(ws, L.off_ctl32), at<double>(ws, L.off_part32),
+                                 at<double>(ws, L.off_chunk32), st);
         if (cs != CBS_OK) return cs;
         done = true;
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1288,6 +1303,12 @@ cbs_status cbs_pass_timing(cbs_medium m, int32_t enable) {
         t.used = 0;
     }
     t.on = enable != 0;
+    return CBS_OK;
+}
+
+cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask) {
+    if (!m || slot_mask < 0 || slot_mask > 0x3f) return CBS_E_INVALID;
+    m->timing.mask = slot_mask;
     return CBS_OK;
 }
 

@@ -11,6 +11,9 @@ struct alignas(2 * sizeof(T)) cx {
     T re, im;
 };
 
+// Partial-sum pairs one reduction block folds.
+constexpr int kReduceChunk = 4096;
+
 // Per-solve control block in device memory.  Written by the reduction
 // kernels, read by every pass kernel (a finished slot's passes exit at once)
 // and polled by the host every few iterations.
@@ -52,6 +55,7 @@ struct Slot {
     T inv_ntot;           // 1 / prod(n)
     cx<T> al1, al2;       // a + lam
     cx<T> ca;             // lam1 / al1
+    cx<T> can;            // lam1 / al1 / prod(n)
     cx<T> cp;             // lam2 * al1
     cx<T> al12;           // al1 * al2
     int adjoint;
@@ -61,8 +65,6 @@ struct Slot {
     double* chunks;       // 2 doubles per block of the reduction
 };
 
-// Partial-sum pairs one reduction block folds.
-constexpr int kReduceChunk = 4096;
 
 struct Geom {
     int ndim;

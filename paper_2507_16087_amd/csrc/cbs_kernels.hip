@@ -51,9 +51,13 @@ template <typename T>
 __device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.re, -a.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.im, a.re}; }   // i a
+// 1 / a with the hardware reciprocal (1 ulp) in FP32, exact division in FP64.
 template <typename T>
-__device__ __forceinline__ cx<T> cinv(cx<T> a) {
-    T d = T(1) / (a.re * a.re + a.im * a.im);
+__device__ __forceinline__ cx<T> cinv_fast(cx<T> a) {
+    const T n = a.re * a.re + a.im * a.im;
+    T d;
+    if constexpr (sizeof(T) == 4) d = __builtin_amdgcn_rcpf(n);
+    else d = T(1) / n;
     return {a.re * d, -a.im * d};
 }
 template <typename T>
@@ -423,6 +427,37 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
     }
 }
 
+// Final step of a norm reduction: the slot's control block from the two
+// totals.  CBS: advance the iteration counter, relative update
+// |dx| / |x_k| (not tested while x_k = 0, the first iteration), done on
+// tolerance, cap, non-finite values or three consecutive updates above twice
+// the iterate.  APPLY: |r|^2, |y|^2 and |r| for the refinement kernels.
+template <bool CBSMODE>
+__device__ void finalize_ctl(Ctl* c, double a, double b) {
+    if (!CBSMODE) {
+        c->res2 = a;
+        c->rhs2 = b;
+        c->scale = sqrt(a);
+        c->res_done += 1;
+        return;
+    }
+    const int it = c->iter + 1;
+    c->iter = it;
+    const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+    c->rel_update = rel;
+    c->xnorm2 = b;
+    int done = RUNNING;
+    if (!isfinite(a) || !isfinite(b)) {
+        done = DIVERGED;
+    } else {
+        c->grow = (it >= 3 && rel > 2.0) ? c->grow + 1 : 0;
+        if (c->grow >= 3) done = DIVERGED;
+        else if (b > 0.0 && rel <= c->tol) done = CONVERGED;
+        else if (it >= c->max_iter) done = CAPPED;
+    }
+    c->done = done;
+}
+
 // --------------------------------- passes A / E: last (contiguous) axis --
 // One work-group owns P whole pencils of one field; TPC lane-fastest threads
 // per pencil, so each stage-0 load and last-stage store of a pencil is one
@@ -442,7 +477,7 @@ enum Kind { FIRST = 0, LAST = 1, FUSED = 2 };
 //   while the transform runs; 2 prefetches x and the medium only.
 template <class P, int MODE, int KIND, int PF, typename T>
 __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ slots, Geom g, int pcols) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
     if (MODE == CBS && s.ctl->done) return;
@@ -614,7 +649,7 @@ template <class P, int DIR, typename T>
 __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slots, Geom g, int axis,
                                                  int pcols, int ldp, int64_t es, int64_t ostride,
                                                  int nlast_tiles, int skip_done, int xg) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
     if (skip_done && s.ctl->done) return;
@@ -650,13 +685,13 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 // FFT.  MODE CBS applies (L+I)^{-1} of App. B.1 (rank-one form, conjugate
 // transpose for the adjoint); MODE APPLY applies the scaled staggered
 // derivative block of L (negated for the adjoint).  1/prod(n) is folded in.
+//   VAR 0: one LDS tile, fields in turn; 1: one region per field, every
+//   exchange shared by all fields; 2: two regions, fields in pairs.
 template <class P, int MODE, int VAR, typename T>
 __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols, int ldp,
                                               int64_t es, int64_t ostride, int nlast_tiles, int xg) {
-    // VAR 0: one LDS tile, fields in turn; 1: one region per field, every
-    // exchange shared by all fields; 2: two regions, fields in pairs.
     constexpr int NR = VAR == 1 ? 4 : (VAR == 2 ? 2 : 1);
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
     if (MODE == CBS && s.ctl->done) return;
@@ -664,10 +699,6 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     const int D = g.ndim, F = D + 1;
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
-    const int io = tile / nlast_tiles;                              // index along the middle axis (3-D)
-    const int il = (tile % nlast_tiles) * pcols + col;              // index along the last axis
-    cx<T>* __restrict__ wt = s.w + (int64_t)io * ostride + (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
     // LDS: NR field tiles | twiddles (N) | k0 S0 (N) | k0 (N)
     const int field_elems = (int)(tile_bytes<T>((size_t)N * ldp) / sizeof(cx<T>));
@@ -679,142 +710,166 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
         k0_l[i] = s.kv[0][i];
         g0_l[i] = rmul(s.kv[0][i], s.sh[0][i]);
     }
-    __syncthreads();
     const cx<T>* tw = tw_l;
-
-    // wavevector components of this column (axes 1.., FFT order)
-    T kc[2];
-    cx<T> gc[2];   // k S for the column axes
-    if (D == 3) {
-        kc[0] = s.kv[1][io];
-        gc[0] = rmul(kc[0], s.sh[1][io]);
-        kc[1] = s.kv[2][il];
-        gc[1] = rmul(kc[1], s.sh[2][il]);
-    } else {
-        kc[0] = s.kv[1][il];
-        gc[0] = rmul(kc[0], s.sh[1][il]);
-        kc[1] = 0;
-        gc[1] = {0, 0};
-    }
-
-    cx<T> v[4][E];
     using QF = Seq<P, -1>;
-    // issue every field's loads before the first transform
+    using QI = Seq<P, 1>;
     constexpr int R0 = QF::r(0);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        if (f < F) {
-            const cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
-#pragma unroll
-            for (int b = 0; b < N / (R0 * P::TPC); ++b)
-#pragma unroll
-                for (int r = 0; r < R0; ++r)
-                    v[f][b * R0 + r] = wf[(uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32];
-        }
-    }
-    if constexpr (NR == 4) {
-        fft_regs_multi<P, -1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
-    } else if constexpr (NR == 2) {
-        fft_regs_multi<P, -1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
-        __syncthreads();
-        fft_regs_multi<P, -1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
-    } else {
+    constexpr int Rl = QF::r(P::S - 1);
+    constexpr int RL = QI::r(P::S - 1);
+
+    // first-stage inputs of every field of one tile, straight from HBM
+    auto load = [&](cx<T> (&v)[4][E], const cx<T>* __restrict__ wt) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             if (f < F) {
-                if (f > 0) __syncthreads();
-                fft_regs<P, -1>(v[f], lds, ldp, col, lane, tw);
+                const cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
+#pragma unroll
+                for (int b = 0; b < N / (R0 * P::TPC); ++b)
+#pragma unroll
+                    for (int r = 0; r < R0; ++r)
+                        v[f][b * R0 + r] = wf[(uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32];
             }
         }
-    }
+    };
 
-    // per-wavevector operator on the registers
-    constexpr int Rl = QF::r(P::S - 1);
-    const T sig = s.adjoint ? T(-1) : T(1);
+    // transforms, operator and stores of one tile whose registers are loaded;
+    // the LDS regions must be free on entry
+    auto run = [&](cx<T> (&v)[4][E], int io, int il, cx<T>* __restrict__ wt) {
+        // wavevector components of this column (axes 1.., FFT order)
+        T kc[2];
+        cx<T> gc[2];   // k S for the column axes
+        if (D == 3) {
+            kc[0] = s.kv[1][io];
+            gc[0] = rmul(kc[0], s.sh[1][io]);
+            kc[1] = s.kv[2][il];
+            gc[1] = rmul(kc[1], s.sh[2][il]);
+        } else {
+            kc[0] = s.kv[1][il];
+            gc[0] = rmul(kc[0], s.sh[1][il]);
+            kc[1] = 0;
+            gc[1] = {0, 0};
+        }
+        if constexpr (NR == 4) {
+            fft_regs_multi<P, -1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+        } else if constexpr (NR == 2) {
+            fft_regs_multi<P, -1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
+            __syncthreads();
+            fft_regs_multi<P, -1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
+        } else {
 #pragma unroll
-    for (int b = 0; b < N / (Rl * P::TPC); ++b) {
-#pragma unroll
-        for (int r = 0; r < Rl; ++r) {
-            const int k0i = out_index<P, -1>(lane, b, r);
-            const int e = b * Rl + r;
-            const T k0 = k0_l[k0i];
-            const cx<T> g0 = g0_l[k0i];
-            cx<T> gg[3] = {g0, gc[0], gc[1]};
-            const cx<T> wp = (D == 3) ? v[3][e] : v[2][e];
-            // t = sum_eta conj(k_eta S_eta) w_eta
-            cx<T> t = cmulc(v[0][e], gg[0]);
-            t = t + cmulc(v[1][e], gg[1]);
-            if (D == 3) t = t + cmulc(v[2][e], gg[2]);
-            if constexpr (MODE == CBS) {
-                const T kk = k0 * k0 + kc[0] * kc[0] + kc[1] * kc[1];
-                cx<T> mu = {kk + s.al12.re, s.adjoint ? -s.al12.im : s.al12.im};
-                cx<T> imu = rmul(s.inv_ntot, cinv(mu));
-                const cx<T> ca = s.adjoint ? conjg(s.ca) : s.ca;
-                const cx<T> cp = s.adjoint ? conjg(s.cp) : s.cp;
-                // u_eta: ca (w_eta - g_eta t / mu) - i sig s g_eta wp / mu
-                const cx<T> tm = cmul(t, imu);
-                const cx<T> pm = rmul(sig * s.s, mul_i(cmul(wp, imu)));
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    if (d < D) {
-                        const cx<T> a = rmul(s.inv_ntot, v[d][e]) - cmul(gg[d], tm);
-                        v[d][e] = cmul(ca, a) - cmul(gg[d], pm);
-                    }
+            for (int f = 0; f < 4; ++f) {
+                if (f < F) {
+                    if (f > 0) __syncthreads();
+                    fft_regs<P, -1>(v[f], lds, ldp, col, lane, tw);
                 }
-                // p: -i sig s t / mu + cp wp / mu
-                const cx<T> pz = cmul(cp, cmul(wp, imu)) - rmul(sig * s.s, mul_i(tm));
-                if (D == 3) v[3][e] = pz;
-                else v[2][e] = pz;
-            } else {
-                // (L - diag) x in scaled form: u_eta = i sig g_eta p / s ; p = i sig t / s
-                const T c = sig * s.inv_ntot / s.s;
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    if (d < D) v[d][e] = rmul(c, mul_i(cmul(gg[d], wp)));
-                if (D == 3) v[3][e] = rmul(c, mul_i(t));
-                else v[2][e] = rmul(c, mul_i(t));
             }
         }
-    }
 
-    // inverse FFT from the registers and store
-    using QI = Seq<P, 1>;
-    constexpr int RL = QI::r(P::S - 1);
-    if constexpr (NR == 4) {
-        __syncthreads();
-        fft_regs_multi<P, 1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
-    } else if constexpr (NR == 2) {
-        __syncthreads();
-        fft_regs_multi<P, 1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
-        __syncthreads();
-        fft_regs_multi<P, 1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
-    }
+        // slot constants of the operator, conjugated for the adjoint (sign
+        // flips of uniform values only, so they stay in scalar registers);
+        // can carries the 1/prod(n) of the inverse transform
+        const cx<T> ca = s.adjoint ? conjg(s.ca) : s.ca;
+        const cx<T> cp = s.adjoint ? conjg(s.cp) : s.cp;
+        const cx<T> can = s.adjoint ? conjg(s.can) : s.can;
+        const T al12im = s.adjoint ? -s.al12.im : s.al12.im;
+        const T ss = s.adjoint ? -s.s : s.s;   // sig s
+        // per-wavevector operator on the registers
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        if (f < F) {
-            if constexpr (NR == 1) {
-                __syncthreads();
-                fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
+        for (int b = 0; b < N / (Rl * P::TPC); ++b) {
+#pragma unroll
+            for (int r = 0; r < Rl; ++r) {
+                const int k0i = out_index<P, -1>(lane, b, r);
+                const int e = b * Rl + r;
+                const T k0 = k0_l[k0i];
+                const cx<T> g0 = g0_l[k0i];
+                cx<T> gg[3] = {g0, gc[0], gc[1]};
+                const cx<T> wp = (D == 3) ? v[3][e] : v[2][e];
+                // t = sum_eta conj(k_eta S_eta) w_eta
+                cx<T> t = cmulc(v[0][e], gg[0]);
+                t = t + cmulc(v[1][e], gg[1]);
+                if (D == 3) t = t + cmulc(v[2][e], gg[2]);
+                if constexpr (MODE == CBS) {
+                    const T kk = k0 * k0 + kc[0] * kc[0] + kc[1] * kc[1];
+                    const cx<T> mu = {kk + s.al12.re, al12im};
+                    const cx<T> imu = rmul(s.inv_ntot, cinv_fast(mu));
+                    // u_eta = ca (w_eta - g_eta t / mu) - i sig s g_eta wp / mu,
+                    // p = -i sig s t / mu + cp wp / mu  (1/prod(n) inside imu)
+                    const cx<T> tm = cmul(t, imu);
+                    const cx<T> wpm = cmul(wp, imu);
+                    if constexpr (sizeof(T) == 4) {
+                        // fewer instructions: u_eta = (ca / prod n) w_eta - g_eta h
+                        const cx<T> h = cmul(ca, tm) + rmul(ss, mul_i(wpm));
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            if (d < D) v[d][e] = cmul(can, v[d][e]) - cmul(gg[d], h);
+                    } else {
+                        // fewer live registers in FP64 (two waves per SIMD)
+                        const cx<T> pm = rmul(ss, mul_i(wpm));
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            if (d < D) {
+                                const cx<T> a = rmul(s.inv_ntot, v[d][e]) - cmul(gg[d], tm);
+                                v[d][e] = cmul(ca, a) - cmul(gg[d], pm);
+                            }
+                        }
+                    }
+                    const cx<T> pz = cmul(cp, wpm) - rmul(ss, mul_i(tm));
+                    if (D == 3) v[3][e] = pz;
+                    else v[2][e] = pz;
+                } else {
+                    // (L - diag) x in scaled form: u_eta = i sig g_eta p / s ; p = i sig t / s
+                    const T c = (s.adjoint ? -s.inv_ntot : s.inv_ntot) / s.s;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        if (d < D) v[d][e] = rmul(c, mul_i(cmul(gg[d], wp)));
+                    if (D == 3) v[3][e] = rmul(c, mul_i(t));
+                    else v[2][e] = rmul(c, mul_i(t));
+                }
             }
-            cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
-#pragma unroll
-            for (int b = 0; b < N / (RL * P::TPC); ++b)
-#pragma unroll
-                for (int r = 0; r < RL; ++r)
-                    wf[(uint32_t)col + (uint32_t)out_index<P, 1>(lane, b, r) * es32] = v[f][b * RL + r];
         }
-    }
+
+        // inverse FFT from the registers and store
+        if constexpr (NR == 4) {
+            __syncthreads();
+            fft_regs_multi<P, 1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+        } else if constexpr (NR == 2) {
+            __syncthreads();
+            fft_regs_multi<P, 1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
+            __syncthreads();
+            fft_regs_multi<P, 1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (f < F) {
+                if constexpr (NR == 1) {
+                    __syncthreads();
+                    fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
+                }
+                cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
+#pragma unroll
+                for (int b = 0; b < N / (RL * P::TPC); ++b)
+#pragma unroll
+                    for (int r = 0; r < RL; ++r)
+                        wf[(uint32_t)col + (uint32_t)out_index<P, 1>(lane, b, r) * es32] = v[f][b * RL + r];
+            }
+        }
+    };
+
+    // tile: index io along the middle axis (3-D), columns along the last
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
+    cx<T>* wt = s.w + (int64_t)(tile / nlast_tiles) * ostride + (int64_t)(tile % nlast_tiles) * pcols;
+    cx<T> v[4][E];
+    __syncthreads();   // tables staged
+    load(v, wt);
+    run(v, (int)(tile / nlast_tiles), (int)(tile % nlast_tiles) * pcols + col, wt);
 }
 
 // ---------------------------------------------------------- reductions --
 // Two levels, one launch: grid = (blocks, slots); block b folds partial pairs
 // [b * kReduceChunk, (b + 1) * kReduceChunk) into chunks[b]; the block that
 // arrives last folds the chunk sums in index order (so the totals do not
-// depend on scheduling) and finalises the slot's control block.
-//   CBS: advance the iteration counter, relative update |dx| / |x_k| (not
-//   tested while x_k = 0, the first iteration), done on tolerance, cap,
-//   non-finite values or three consecutive updates above twice the iterate.
-//   APPLY: |r|^2, |y|^2 and |r| for the refinement kernels.
+// depend on scheduling) and finalises the slot's control block
+// (finalize_ctl).
 template <typename T, bool CBSMODE>
 __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* slots, int nparts) {
     __shared__ double red[16];
@@ -848,28 +903,7 @@ __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* slots, int nparts
         b += ((volatile double*)s.chunks)[2 * i + 1];
     }
     c->arrive = 0;
-    if (!CBSMODE) {
-        c->res2 = a;
-        c->rhs2 = b;
-        c->scale = sqrt(a);
-        c->res_done += 1;
-        return;
-    }
-    const int it = c->iter + 1;
-    c->iter = it;
-    const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
-    c->rel_update = rel;
-    c->xnorm2 = b;
-    int done = RUNNING;
-    if (!isfinite(a) || !isfinite(b)) {
-        done = DIVERGED;
-    } else {
-        c->grow = (it >= 3 && rel > 2.0) ? c->grow + 1 : 0;
-        if (c->grow >= 3) done = DIVERGED;
-        else if (b > 0.0 && rel <= c->tol) done = CONVERGED;
-        else if (it >= c->max_iter) done = CAPPED;
-    }
-    c->done = done;
+    finalize_ctl<CBSMODE>(c, a, b);
 }
 
 __global__ void k_ctl_reset(Ctl* c, int max_iter, double tol) {
@@ -1046,7 +1080,8 @@ __global__ void k_gradient(Geom g, const double* c, const double* rho, const dou
     X(96, 4, 4, 6, 8)                 \
     X(128, 8, 16, 1, 8)               \
     X(192, 4, 4, 12, 16)              \
-    X(256, 16, 16, 1, 16)
+    X(256, 16, 16, 1, 16)             \
+    X(512, 8, 8, 8, 64)
 
 // Alternative plans with fewer elements per thread (for register-heavy
 // passes in FP64).
@@ -1091,23 +1126,25 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         const size_t lr = std::max(tile_bytes<T>((size_t)pcols * lds_pitch<ROWS>(N, 0)), (size_t)(64 * sizeof(double))) +
                           (size_t)N * (sizeof(cx<T>) + sizeof(T));
         if (lr > kMaxLdsBytes) return hipErrorInvalidConfiguration;
+        // last-axis inverse passes: the variant is the prefetch
+        const int pf = variant;
 #define LA_LAUNCH(M, K, PF_) hipLaunchKernelGGL((k_lastaxis<P, M, K, PF_, T>), grid, blk, lr, st, slots, g, pcols)
         if (kind == 0) {
             if (mode == CBS) LA_LAUNCH(CBS, FIRST, 0);
             else LA_LAUNCH(APPLY, FIRST, 0);
         } else if (kind == 1) {
             if (mode == CBS) {
-                if (variant == 1) LA_LAUNCH(CBS, LAST, 1);
-                else if (variant == 2) LA_LAUNCH(CBS, LAST, 2);
+                if (pf == 1) LA_LAUNCH(CBS, LAST, 1);
+                else if (pf == 2) LA_LAUNCH(CBS, LAST, 2);
                 else LA_LAUNCH(CBS, LAST, 0);
             } else {
-                if (variant == 1) LA_LAUNCH(APPLY, LAST, 1);
-                else if (variant == 2) LA_LAUNCH(APPLY, LAST, 2);
+                if (pf == 1) LA_LAUNCH(APPLY, LAST, 1);
+                else if (pf == 2) LA_LAUNCH(APPLY, LAST, 2);
                 else LA_LAUNCH(APPLY, LAST, 0);
             }
         } else {
-            if (variant == 1) LA_LAUNCH(CBS, FUSED, 1);
-            else if (variant == 2) LA_LAUNCH(CBS, FUSED, 2);
+            if (pf == 1) LA_LAUNCH(CBS, FUSED, 1);
+            else if (pf == 2) LA_LAUNCH(CBS, FUSED, 2);
             else LA_LAUNCH(CBS, FUSED, 0);
         }
 #undef LA_LAUNCH

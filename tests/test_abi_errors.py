@@ -45,7 +45,7 @@ def test_invalid_medium_values(bad):
 
 
 @pytest.mark.parametrize("n,code", [((10, 16, 16), L.CBS_E_UNSUPPORTED), ((16, 7, 16), L.CBS_E_UNSUPPORTED),
-                                    ((512, 16, 16), L.CBS_E_UNSUPPORTED)])
+                                    ((1024, 16, 16), L.CBS_E_UNSUPPORTED), ((384, 8, 8), L.CBS_E_UNSUPPORTED)])
 def test_unsupported_sizes(n, code):
     shape = n
     ones = np.ones(shape)
@@ -72,6 +72,8 @@ def test_invalid_dimension_and_null_pointers():
     assert L.lib().cbs_destroy_medium(None) == L.CBS_E_INVALID
     b = C.c_size_t()
     assert L.lib().cbs_workspace_bytes(None, 0, 1, C.byref(b)) == L.CBS_E_INVALID
+    assert L.lib().cbs_pass_timing(None, 1) == L.CBS_E_INVALID
+    assert L.lib().cbs_pass_timing_slots(None, 0x3F) == L.CBS_E_INVALID
 
 
 def test_batch_workspace_size_query_on_cpu():

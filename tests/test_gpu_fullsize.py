@@ -79,7 +79,8 @@ def test_shell256_refined_accuracy(cbs, shell, report):
     """The skull-like case is ill-conditioned: the error is ~40x the scaled
     residual, for FP64 and refined FP32 alike.  A 1e-5 error therefore needs a
     residual of ~1e-7; both paths are solved to 1e-7 and compared with the
-    FP64 solution at 1e-10 (itself iterate-pinned to the oracle above)."""
+    FP64 solution at 1e-8 (error <= ~4e-7, 25x below the gate; FP64 itself is
+    iterate-pinned to the oracle above)."""
     import torch
     from paper_2507_16087_amd import _lib
     pr, gm, om = shell
@@ -95,13 +96,14 @@ def test_shell256_refined_accuracy(cbs, shell, report):
     r_orc = om.rel_residual(shat, xi)
     del shat, xi, u32
     assert abs(r_orc - i32["rel_residual"]) <= 1e-3 * i32["rel_residual"] + 1e-12
-    report("shell3d 256^3: FP64 reference solve to 1e-10")
-    ref, _, iref = cbs.solve(gm, sp, tol=1e-10, prec="fp64", max_iter=400000, check_every=200,
+    report("shell3d 256^3: FP64 reference solve to 1e-8")
+    ref, _, iref = cbs.solve(gm, sp, tol=1e-8, prec="fp64", max_iter=400000, check_every=200,
                              stop_rule=_lib.CBS_STOP_RESIDUAL, want_u=False)
     report(f"  {iref['iterations']} iterations; FP64 solve to 1e-7")
     assert iref["converged"]
     p64, _, i64 = cbs.solve(gm, sp, tol=1e-7, prec="fp64", max_iter=400000, check_every=50,
                             stop_rule=_lib.CBS_STOP_RESIDUAL, want_u=False)
+    report(f"  {i64['iterations']} iterations")
     e32 = (torch.linalg.norm(p32 - ref) / torch.linalg.norm(ref)).item()
     e64 = (torch.linalg.norm(p64 - ref) / torch.linalg.norm(ref)).item()
     print(f"256^3 shell at residual 1e-7: refined FP32 error {e32:.2e} "

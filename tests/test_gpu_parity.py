@@ -174,14 +174,15 @@ def _plan(gm, prec, kind):
 
 
 @pytest.mark.parametrize("pin", [("CBS_PROP_VARIANT", 0), ("CBS_PROP_VARIANT", 1), ("CBS_PROP_VARIANT", 2),
-                                 ("CBS_LAST_VARIANT", 1), ("CBS_LAST_VARIANT", 2)])
+                                 ("CBS_LAST_VARIANT", 0), ("CBS_LAST_VARIANT", 1), ("CBS_LAST_VARIANT", 2)])
 @pytest.mark.parametrize("shape", [(48, 32), (16, 24, 32), (64, 8, 16), (256, 4, 8)])
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_pass_variants_match_oracle(orc, cbs, monkeypatch, pin, shape, adjoint):
     """Every pass variant the tuner may pick, pinned in turn, against the
     oracle: the propagator's LDS layouts (one tile reused field by field, one
     region per field, fields in pairs) and the last-axis inverse pass's
-    prefetch of x, y and the medium.  FP64 iterates and the refined FP32 solve."""
+    prefetch of x, y and the medium.  FP64 iterates and the refined FP32
+    solve."""
     name, variant = pin
     monkeypatch.setenv(name, str(variant))
     kind = 4 if name == "CBS_PROP_VARIANT" else 1
@@ -200,4 +201,25 @@ def test_pass_variants_match_oracle(orc, cbs, monkeypatch, pin, shape, adjoint):
                            adjoint=adjoint)
     assert info["converged"]
     assert _plan(gm, "fp32_refined", kind)["variant"] == variant
+    assert _rel(p, xs[-1]) <= 1e-5 and _rel(u, xs[:-1]) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(512, 4, 8), (4, 512, 8), (4, 8, 512), (512, 8), (8, 512)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_plan512_matches_oracle(orc, cbs, shape, adjoint):
+    """The 512-point plan (radix 8 x 8 x 8) on every axis role: axis-0
+    propagator pass, strided axis-1 pass, last-axis passes; FP64 iterates
+    and the refined solve against the oracle."""
+    om, gm = _pair(orc, cbs, shape, pml=1, seed=8)
+    F = len(shape) + 1
+    s = np.zeros((F,) + shape, complex)
+    flat = s.reshape(F, -1)
+    flat[-1, [11, 3001]] = [1.0, 0.3 - 0.2j]
+    xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=30, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=0.0, max_iter=30, adjoint=adjoint)
+    assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
+    xs, _ = om.solve(om.source_hat(s), tol=1e-12, max_iter=200000, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=1e-7, prec="fp32_refined", inner_tol=1e-4,
+                           adjoint=adjoint)
+    assert info["converged"]
     assert _rel(p, xs[-1]) <= 1e-5 and _rel(u, xs[:-1]) <= 1e-5

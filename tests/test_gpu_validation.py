@@ -5,6 +5,9 @@
   of 128^3, 192^3 and 256^3: the central slice against the series solution;
   the error must fall with resolution (staircasing) and stay below 3 % at 16
   points per wavelength.
+* The same sphere staggered vs collocated (App. B accuracy claim), and at
+  the paper's own scale (24 points per wavelength, 4-wavelength layer,
+  512^3, tolerance 1e-4, 150-term series).
 * The paper's 2-D disks example (256^2, 500 kHz, c 3500 / rho 3000 /
   alpha 10 dB/cm inclusions, line source): FP64 iterates against the oracle,
   and the converged field's residual evaluated by the oracle's operator.
@@ -28,7 +31,7 @@ def cbs():
     return solver
 
 
-def _sphere_error(cbs, ppw, n):
+def _sphere_error(cbs, ppw, n, collocated=False):
     from oracle import analytic
     lam = C0 / F0
     dx = lam / ppw
@@ -42,7 +45,7 @@ def _sphere_error(cbs, ppw, n):
     rho = np.where(inside, 1.5 * RHO0, RHO0)
     src = np.array([ctr[0] - int(round(4 * ppw)), ctr[1], ctr[2]])
     pml = int(round(2 * ppw))
-    m = cbs.Medium(shape, dx, 2 * np.pi * F0, c, rho, np.zeros(shape), pml=pml)
+    m = cbs.Medium(shape, dx, 2 * np.pi * F0, c, rho, np.zeros(shape), pml=pml, collocated=collocated)
     sp = np.zeros(shape, complex)
     sp[tuple(src)] = 1.0
     p, _, info = cbs.solve(m, sp, tol=1e-7, prec="fp32_refined", want_u=False, check_every=50)
@@ -67,6 +70,72 @@ def test_sphere_series_converges_with_resolution(cbs, report):
     print("sphere errors at 8/12/16 PPW:", errs)
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.03
+
+
+@pytest.mark.timeout(600)
+def test_sphere_staggered_closer_than_collocated(cbs, report):
+    """App. B's accuracy claim on the sphere: at 8 and 12 points per
+    wavelength the staggered grid is closer to the series than the collocated
+    one (same medium, source and solver tolerance)."""
+    for ppw, n in ((8, 128), (12, 192)):
+        report(f"sphere series, staggered vs collocated: {ppw} points per wavelength on {n}^3")
+        es = _sphere_error(cbs, ppw, n)
+        ec = _sphere_error(cbs, ppw, n, collocated=True)
+        report(f"  staggered {es:.3e}, collocated {ec:.3e}")
+        assert es < ec, (ppw, es, ec)
+
+
+@pytest.mark.timeout(900)
+def test_sphere_paper_scale(cbs, report):
+    """The paper's sphere experiment at its own scale: sphere radius 2
+    wavelengths (0.4 m at a 0.2 m wavelength), contrast 1.5 in c and rho,
+    point source 5 wavelengths from the centre, a cube of 10.5 wavelengths,
+    24 points per wavelength, an absorbing layer 4 wavelengths thick, relative
+    tolerance 1e-4, series with 150 terms.  The grid is 512^3: the layer takes
+    96 cells per side and the 320-cell interior holds the 252-cell cube.  The
+    central slice over the cube, outside one wavelength around the source,
+    against the series."""
+    import torch
+    from oracle import analytic
+    lam = C0 / F0
+    ppw, n, pml = 24, 512, 96
+    dx = lam / ppw
+    shape = (n, n, n)
+    ctr = np.array([n // 2] * 3)
+    R = 2.0 * lam
+    report("paper-scale sphere: building the 512^3 medium")
+    ax = (np.arange(n, dtype=np.float32) - ctr[0]) ** 2
+    r2 = ax[:, None, None] + ax[None, :, None] + ax[None, None, :]
+    inside = r2 * np.float32(dx * dx) < np.float32(R * R)
+    del r2
+    c = np.where(inside, 1.5 * C0, C0)
+    rho = np.where(inside, 1.5 * RHO0, RHO0)
+    del inside
+    src = np.array([ctr[0] - 5 * ppw, ctr[1], ctr[2]])
+    m = cbs.Medium(shape, dx, 2 * np.pi * F0, c, rho, np.zeros(shape), pml=pml)
+    del c, rho
+    sp = torch.zeros(n ** 3, dtype=torch.complex128, device="cuda")
+    sp[int(np.ravel_multi_index(tuple(src), shape))] = 1.0
+    report("paper-scale sphere: refined solve to 1e-4")
+    p, _, info = cbs.solve(m, sp, tol=1e-4, prec="fp32_refined", want_u=False, check_every=50)
+    report(f"  {info['iterations']} iterations, {info['seconds']:.1f} s; series on the central slice")
+    assert info["converged"]
+    sl = p.reshape(shape)[:, :, ctr[2]].cpu().numpy()
+    del p, m
+    half = 126                                    # the 2.1 m cube: 252 cells
+    lo, hi = ctr[0] - half, ctr[0] + half
+    i0, i1 = np.meshgrid(np.arange(lo, hi), np.arange(lo, hi), indexing="ij")
+    pos = np.stack([i0.ravel(), i1.ravel(), np.full(i0.size, ctr[2])], 1) * dx
+    d = np.hypot(i0 - src[0], i1 - src[1]) * dx
+    sel = d > lam
+    ref = analytic.sphere_series(pos[sel.ravel()], ctr * dx, src * dx, R, C0, RHO0, 1.5 * C0,
+                                 1.5 * RHO0, 2 * np.pi * F0, mmax=150, sp_dx3=dx ** 3)
+    got = sl[lo:hi, lo:hi][sel]
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    report(f"  relative error on the slice {err:.3e}")
+    print(f"paper-scale sphere (24 points per wavelength, 512^3): error {err:.3e}, "
+          f"{info['iterations']} iterations")
+    assert err < 0.02
 
 
 def test_disks2d_iterates_and_residual(cbs, orc):
