@@ -207,15 +207,17 @@ cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
 
 /* Pass plans in use for precision prec (after the first solve tunes them):
  * out[4 i + 0..3] = kind, axis length, columns per work-group, flags of pass i
- * (kind -1 = unused; flag bit 0 = wide radix split, bits 1-2 = variant: for
+ * (kind -1 = unused; flag bit 0 = wide radix split, bits 1-3 = variant: for
  * the propagator pass the LDS layout -- 0 one tile reused field by field, 1
  * one region per field with every exchange shared, 2 two regions with fields
- * in pairs; for the last-axis inverse pass the prefetch -- 0 none, 1 x, y
- * and the medium issued before the transform, 2 x and the medium).  The
- * first solve of each (shape, precision) in a process times the candidate
- * plans on its workspace and keeps the fastest (set CBS_AUTOTUNE=0 in the
- * environment to keep the defaults; CBS_PROP_VARIANT and CBS_LAST_VARIANT =
- * 0, 1 or 2 pin the two variants, tuned or not).
+ * in pairs, plus 4 when the column tile has no row padding; for the strided
+ * passes 4 = no row padding; for the last-axis inverse pass the prefetch --
+ * 0 none, 1 x, y and the medium issued before the transform, 2 x and the
+ * medium).  The first solve of each (shape, precision) in a process times the
+ * candidate plans on its workspace and keeps the fastest (set CBS_AUTOTUNE=0
+ * in the environment to keep the defaults; CBS_PROP_VARIANT (0, 1, 2, 4, 5,
+ * 6), CBS_LAST_VARIANT (0, 1, 2) and CBS_STRIDED_VARIANT (0, 4) pin the
+ * variants, tuned or not).
  * Configurations needing more than 160 KiB of LDS are never launched. */
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
 

@@ -76,8 +76,9 @@ struct Pass {
     int n;
     int pcols;
     bool wide;
-    int variant;   // propagator: LDS regions (0 one, 1 per field, 2 two);
-                   // last-axis inverse: prefetch (0 none, 1 x y medium, 2 x medium)
+    int variant;   // propagator: LDS regions (bits 0-1: 0 one, 1 per field, 2 two);
+                   // last-axis inverse: prefetch (0 none, 1 x y medium, 2 x medium);
+                   // strided and propagator: bit 2 = unpadded column tile
 };
 
 struct PassSet {
@@ -443,26 +444,31 @@ hipError_t run_passes(cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T
 // every medium of one shape runs the same kernels (results of a solve do not
 // depend on which other solves ran first).  CBS_AUTOTUNE=0 keeps the defaults.
 struct TuneKey {
-    int ndim, n0, n1, n2, fp64, prop_variant, last_variant;
+    int ndim, n0, n1, n2, fp64, prop_variant, last_variant, strided_variant;
     bool operator<(const TuneKey& o) const {
-        return std::tie(ndim, n0, n1, n2, fp64, prop_variant, last_variant) <
-               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant, o.last_variant);
+        return std::tie(ndim, n0, n1, n2, fp64, prop_variant, last_variant, strided_variant) <
+               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant, o.last_variant, o.strided_variant);
     }
 };
 
 // Variants a pass kind may take: the propagator's LDS layouts (0 one tile
 // reused field by field, 1 one region per field, 2 two regions with fields in
 // pairs); the last-axis inverse pass's prefetch (0 none, 1 x, y and medium,
-// 2 x and medium).
+// 2 x and medium).  Bit 2 of a strided or propagator variant drops the
+// one-element row padding of the column tile.
 std::vector<int> variants_of(int kind) {
-    if (kind == 4 || kind == 1) return {0, 1, 2};
+    if (kind == 4) return {0, 1, 2, 4, 5, 6};
+    if (kind == 1) return {0, 1, 2};
+    if (kind == 2 || kind == 3) return {0, 4};
     return {0};
 }
 
-// CBS_PROP_VARIANT pins the propagator pass and CBS_LAST_VARIANT the
-// last-axis inverse pass to one of their variants; unset, all compete.
+// CBS_PROP_VARIANT pins the propagator pass, CBS_LAST_VARIANT the last-axis
+// inverse pass and CBS_STRIDED_VARIANT the strided passes to one of their
+// variants; unset, all compete.
 int forced_variant(int kind) {
-    const char* e = std::getenv(kind == 4 ? "CBS_PROP_VARIANT" : "CBS_LAST_VARIANT");
+    const char* name = kind == 4 ? "CBS_PROP_VARIANT" : (kind == 1 ? "CBS_LAST_VARIANT" : "CBS_STRIDED_VARIANT");
+    const char* e = std::getenv(name);
     if (!e || e[0] < '0' || e[0] > '9' || e[1] != 0) return -1;
     const int v = e[0] - '0';
     for (int ok : variants_of(kind))
@@ -620,7 +626,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
     if (!autotune_enabled()) {
         for (PassSet* ps : {&m->ps64, &m->ps32})
             for (int i = 0; i < ps->count; ++i)
-                if (ps->p[i].kind == 4 || ps->p[i].kind == 1)
+                if (ps->p[i].kind >= 1 && ps->p[i].kind <= 4)
                     ps->p[i].variant = std::max(0, forced_variant(ps->p[i].kind));
         return CBS_OK;
     }
@@ -631,7 +637,8 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         bool& done = fp64 ? m->tuned64 : m->tuned32;
         if (done) continue;
         PassSet& ps = fp64 ? m->ps64 : m->ps32;
-        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_variant(4), forced_variant(1)};
+        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_variant(4), forced_variant(1),
+                          forced_variant(2)};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(key);

@@ -1112,7 +1112,11 @@ template <typename T, class P>
 static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis,
                               int pcols, int variant, hipStream_t st) {
     const int N = P::N;
-    const int ldp = pcols + 1;
+    // column tiles (strided and propagator passes) are padded by one element
+    // per row unless variant bit 2 asks for the unpadded pitch
+    const bool colpass = kind == 2 || kind == 3 || kind == 4;
+    const int ldp = pcols + ((colpass && (variant & 4)) ? 0 : 1);
+    if (colpass) variant &= 3;
     // tile + twiddles + (propagator) k0 S0 and k0 tables
     size_t lds = tile_bytes<T>((size_t)N * ldp) + (size_t)N * (2 * sizeof(cx<T>) + sizeof(T));
     if (lds < 64 * sizeof(double)) lds = 64 * sizeof(double);

@@ -174,18 +174,23 @@ def _plan(gm, prec, kind):
 
 
 @pytest.mark.parametrize("pin", [("CBS_PROP_VARIANT", 0), ("CBS_PROP_VARIANT", 1), ("CBS_PROP_VARIANT", 2),
-                                 ("CBS_LAST_VARIANT", 0), ("CBS_LAST_VARIANT", 1), ("CBS_LAST_VARIANT", 2)])
+                                 ("CBS_PROP_VARIANT", 4), ("CBS_PROP_VARIANT", 5), ("CBS_PROP_VARIANT", 6),
+                                 ("CBS_LAST_VARIANT", 0), ("CBS_LAST_VARIANT", 1), ("CBS_LAST_VARIANT", 2),
+                                 ("CBS_STRIDED_VARIANT", 4)])
 @pytest.mark.parametrize("shape", [(48, 32), (16, 24, 32), (64, 8, 16), (256, 4, 8)])
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_pass_variants_match_oracle(orc, cbs, monkeypatch, pin, shape, adjoint):
     """Every pass variant the tuner may pick, pinned in turn, against the
     oracle: the propagator's LDS layouts (one tile reused field by field, one
-    region per field, fields in pairs) and the last-axis inverse pass's
-    prefetch of x, y and the medium.  FP64 iterates and the refined FP32
-    solve."""
+    region per field, fields in pairs; each with or without row padding of
+    the column tile), the strided passes without row padding, and the
+    last-axis inverse pass's prefetch of x, y and the medium.  FP64 iterates
+    and the refined FP32 solve."""
     name, variant = pin
+    if name == "CBS_STRIDED_VARIANT" and len(shape) == 2:
+        pytest.skip("2-D grids have no strided pass")
     monkeypatch.setenv(name, str(variant))
-    kind = 4 if name == "CBS_PROP_VARIANT" else 1
+    kind = {"CBS_PROP_VARIANT": 4, "CBS_LAST_VARIANT": 1, "CBS_STRIDED_VARIANT": 2}[name]
     om, gm = _pair(orc, cbs, shape, pml=1, seed=5)
     F = len(shape) + 1
     s = np.zeros((F,) + shape, complex)
