@@ -42,7 +42,9 @@
  *    CBS_NOT_CONVERGED the outputs hold the last iterate.
  *  - Threading: a medium is immutable after creation except through
  *    cbs_set_scalars; concurrent calls on one medium must use different
- *    workspaces and streams.
+ *    workspaces and streams (the first solves tune the pass plans once,
+ *    under a lock).  Per-pass timing (cbs_pass_timing*) is a measurement aid
+ *    for one thread at a time.
  */
 #ifndef CBS_H
 #define CBS_H

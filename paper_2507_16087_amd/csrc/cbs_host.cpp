@@ -270,6 +270,7 @@ struct cbs_medium_s {
     double lam1, lam2;
     PassSet ps64, ps32;
     bool tuned64 = false, tuned32 = false;
+    std::mutex tune_mu;   // first solves on several threads tune the pass sets once
     void* dev = nullptr;
     // device pointers into dev
     double *rhobar64, *c64, *rho64, *alpha64;
@@ -623,11 +624,16 @@ bool autotune_enabled() {
 // Tune the pass sets this precision uses, on the caller's workspace (its
 // contents are scratch here), or take them from the process cache.
 cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
+    // Pass sets change only here, under the medium's lock, and only until
+    // they are marked tuned; solves read them after this call returns.
+    std::lock_guard<std::mutex> mlk(m->tune_mu);
     if (!autotune_enabled()) {
+        if (m->tuned64 && m->tuned32) return CBS_OK;
         for (PassSet* ps : {&m->ps64, &m->ps32})
             for (int i = 0; i < ps->count; ++i)
                 if (ps->p[i].kind >= 1 && ps->p[i].kind <= 4)
                     ps->p[i].variant = std::max(0, forced_variant(ps->p[i].kind));
+        m->tuned64 = m->tuned32 = true;
         return CBS_OK;
     }
     const Layout L = layout_for(m, prec);
