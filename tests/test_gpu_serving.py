@@ -108,3 +108,37 @@ def test_batch_rejects_wrong_shape_and_full(cbs):
         pass
     p, _, info = b.retire(0)
     assert info["converged"]
+
+
+def test_concurrent_solves_on_one_medium(cbs):
+    """The ABI lets several threads solve on one medium with their own
+    workspaces and streams; the first solves tune the plans once.  Four
+    threads, fresh medium, must each reproduce the serial result."""
+    import threading
+    import torch
+    pr = _prob(32, 1e6, 77)
+    sp = torch.from_numpy(pr.dense_source().ravel()).cuda()
+    m = _medium(cbs, pr)
+    out = [None] * 4
+    err = []
+
+    def work(i):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                p, _, info = cbs.solve(m, sp, tol=1e-7, prec="fp32_refined", want_u=False, stream=st)
+            st.synchronize()
+            out[i] = (p.cpu().numpy(), info["iterations"])
+        except Exception as e:   # pragma: no cover - reported below
+            err.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not err, err
+    ref, _, iref = cbs.solve(m, sp, tol=1e-7, prec="fp32_refined", want_u=False)
+    for p, it in out:
+        assert it == iref["iterations"]
+        assert _rel(p, ref.cpu().numpy()) <= 1e-12
