@@ -208,26 +208,33 @@ cbs_status cbs_pass_timing(cbs_medium m, int32_t enable);
 cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
 
 /* Pass plans in use for precision prec (after the first solve tunes them):
- * out[4 i + 0..3] = kind, axis length, columns per work-group, flags of pass i
- * (kind -1 = unused; flag bit 0 = wide radix split, bits 1-3 = variant: for
- * the propagator pass the LDS layout -- 0 one tile reused field by field, 1
- * one region per field with every exchange shared, 2 two regions with fields
- * in pairs, plus 4 when the column tile has no row padding; for the strided
- * passes 4 = no row padding; for the last-axis inverse pass the prefetch --
- * 0 none, 1 x, y and the medium issued before the transform, 2 x and the
- * medium).  The first solve of each (shape, precision) in a process times the
- * candidate plans on its workspace and keeps the fastest (set CBS_AUTOTUNE=0
- * in the environment to keep the defaults; CBS_PROP_VARIANT (0, 1, 2, 4, 5,
- * 6), CBS_LAST_VARIANT (0, 1, 2) and CBS_STRIDED_VARIANT (0, 4) pin the
- * variants, tuned or not).
- * Configurations needing more than 160 KiB of LDS are never launched. */
+ * out[4 i + 0..3] = kind, axis length, columns per work-group and flags of
+ * pass i in launch order (kind -1 = unused).  Flags:
+ *   bit 0     wide radix split (fewer elements per thread);
+ *   bits 1-3  variant.  Propagator pass: LDS layout 0 one tile reused field
+ *             by field, 1 one region per field with every exchange shared,
+ *             2 two regions with fields in pairs, plus 4 for a column tile
+ *             without row padding.  Strided passes: 4 = no row padding.
+ *             Last-axis inverse pass: prefetch 0 none, 1 x, y and the medium
+ *             issued before the transform, 2 x and the medium;
+ *   bits 4+   (3-D middle passes) the number of last-axis column blocks the
+ *             forward-axis-1, propagator and inverse-axis-1 passes run in,
+ *             one block after the other so a block's data is still in the
+ *             memory-side cache for its next pass (1 = whole grid).
+ * The first solve of each (shape, precision) in a process times the
+ * candidate plans and block counts on its workspace and keeps the fastest.
+ * Environment: CBS_AUTOTUNE=0 keeps the defaults; CBS_PROP_VARIANT (0, 1, 2,
+ * 4, 5, 6), CBS_LAST_VARIANT (0, 1, 2), CBS_STRIDED_VARIANT (0, 4) and
+ * CBS_COLUMN_BLOCKS (1, 2, 4, 8) pin a choice, tuned or not.  Configurations
+ * needing more than 160 KiB of LDS are never launched. */
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
 
 /* Totals so far: ms[g * 6 + k] and launches[g * 6 + k] for group g (0 FP32
  * CBS iteration, 1 FP64 CBS iteration, 2 FP64 residual) and slot k (0..4 the
  * passes in launch order -- contiguous forward, strided forward, axis-0
- * propagator, strided inverse, contiguous inverse; 2-D grids use slots 0, 1,
- * 2 -- and 5 the reduction). */
+ * propagator, strided inverse, contiguous inverse; 2-D grids use slots 0, 1
+ * and 4 -- and 5 the reduction).  Middle passes run in column blocks count
+ * one launch per block. */
 cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18]);
 
 /* ---------------- batched slots (continuous-batching serving) -------------

@@ -22,7 +22,7 @@ namespace cbs {
 // kernels (cbs_kernels.hip)
 template <typename T>
 hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
-                       int pcols, bool wide, int variant, hipStream_t st);
+                       int pcols, bool wide, int variant, hipStream_t st, int l0 = 0, int lw = 0);
 template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st);
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st);
@@ -84,7 +84,11 @@ struct Pass {
 struct PassSet {
     Pass p[5];
     int count;
-    int nparts;   // partial-sum slots written by the last pass
+    int nparts;    // partial-sum slots written by the last pass
+    // 3-D: the middle passes (forward axis 1, propagator, inverse axis 1) run
+    // block by block over this many equal ranges of last-axis columns, so a
+    // block's data is still in the memory-side cache for its next pass
+    int cblocks = 1;
 };
 
 int pow2_floor_div(int64_t total, int cap) {
@@ -410,22 +414,35 @@ hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int 
                           int nall, const Slot<T>* starts, int nstart, hipStream_t st) {
     const bool timed = tp && tp->on;
     const int group = mode == MODE_APPLY ? 2 : (sizeof(T) == 8 ? 1 : 0);
-    for (int i = 0; i < ps.count; ++i) {
+    auto launch = [&](int i, int l0, int lw) -> hipError_t {
         const Pass& p = ps.p[i];
         const bool pro = mode == MODE_CBS && i == 0;
-        if (pro && nstart == 0) continue;
         const int kind = (mode == MODE_CBS && i == ps.count - 1) ? 5 : p.kind;
         const int slot = i == ps.count - 1 ? 4 : i;
         const bool ev = timed && ((tp->mask >> slot) & 1);
         if (ev && timing_begin(*tp, group * 8 + slot, st) != hipSuccess) return hipErrorUnknown;
         hipError_t e = launch_pass<T>(kind, mode, pro ? starts : all, pro ? nstart : nall, g, p.axis, p.n, p.pcols,
-                                      p.wide, p.variant, st);
+                                      p.wide, p.variant, st, l0, lw);
         if (e != hipSuccess) return e;
         if (ev && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
+        return hipSuccess;
+    };
+    hipError_t e;
+    if (!(mode == MODE_CBS && nstart == 0) && (e = launch(0, 0, 0)) != hipSuccess) return e;
+    if (ps.count == 5 && ps.cblocks > 1) {
+        // middle passes block by block over the last-axis columns
+        const int lw = g.n[g.ndim - 1] / ps.cblocks;
+        for (int b = 0; b < ps.cblocks; ++b)
+            for (int i = 1; i <= 3; ++i)
+                if ((e = launch(i, b * lw, lw)) != hipSuccess) return e;
+    } else {
+        for (int i = 1; i < ps.count - 1; ++i)
+            if ((e = launch(i, 0, 0)) != hipSuccess) return e;
     }
+    if ((e = launch(ps.count - 1, 0, 0)) != hipSuccess) return e;
     const bool ev = timed && ((tp->mask >> 5) & 1);
     if (ev && timing_begin(*tp, group * 8 + 5, st) != hipSuccess) return hipErrorUnknown;
-    hipError_t e = launch_reduce<T>(mode == MODE_CBS, all, ps.nparts, nall, st);
+    e = launch_reduce<T>(mode == MODE_CBS, all, ps.nparts, nall, st);
     if (e != hipSuccess) return e;
     if (ev && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
     return hipSuccess;
@@ -445,10 +462,11 @@ hipError_t run_passes(cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T
 // every medium of one shape runs the same kernels (results of a solve do not
 // depend on which other solves ran first).  CBS_AUTOTUNE=0 keeps the defaults.
 struct TuneKey {
-    int ndim, n0, n1, n2, fp64, prop_variant, last_variant, strided_variant;
+    int ndim, n0, n1, n2, fp64, prop_variant, last_variant, strided_variant, cblocks;
     bool operator<(const TuneKey& o) const {
-        return std::tie(ndim, n0, n1, n2, fp64, prop_variant, last_variant, strided_variant) <
-               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant, o.last_variant, o.strided_variant);
+        return std::tie(ndim, n0, n1, n2, fp64, prop_variant, last_variant, strided_variant, cblocks) <
+               std::tie(o.ndim, o.n0, o.n1, o.n2, o.fp64, o.prop_variant, o.last_variant, o.strided_variant,
+                        o.cblocks);
     }
 };
 
@@ -479,6 +497,24 @@ int forced_variant(int kind) {
 std::mutex g_tune_mu;
 std::map<TuneKey, PassSet> g_tune_cache;
 
+// CBS_COLUMN_BLOCKS pins the block count of the middle passes (1, 2, 4, 8).
+int forced_cblocks() {
+    const char* e = std::getenv("CBS_COLUMN_BLOCKS");
+    if (!e) return -1;
+    const int v = std::atoi(e);
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : -1;
+}
+
+// Blocks must split the last axis into whole column tiles of every middle pass.
+bool cblocks_valid(const Geom& g, const PassSet& ps, int blocks) {
+    if (ps.count != 5) return blocks == 1;
+    const int nl = g.n[g.ndim - 1];
+    if (nl % blocks) return false;
+    for (int i = 1; i <= 3; ++i)
+        if ((nl / blocks) % ps.p[i].pcols) return false;
+    return true;
+}
+
 std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
     std::vector<Pass> out;
     const int last = g.ndim - 1;
@@ -496,9 +532,15 @@ std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
             total = g.n[last];
             cap = std::min(cap, fp64 ? 16 : 32);
         }
+        // a pinned column-block count needs tiles that split each block evenly
+        const int pin = forced_cblocks();
+        const bool middle = g.ndim == 3 && (base.kind == 2 || base.kind == 3 || base.kind == 4);
+        const int lw = (middle && pin > 1 && g.n[last] % pin == 0) ? g.n[last] / pin : 0;
         for (int pc = 1; pc <= cap; pc *= 2) {
             if (total % pc) break;
-            if (pc * tpc < 64 && pc * 2 <= cap && total % (pc * 2) == 0) continue;   // at least a wave
+            if (lw && lw % pc) break;
+            if (pc * tpc < 64 && pc * 2 <= cap && total % (pc * 2) == 0 && !(lw && lw % (pc * 2)))
+                continue;   // at least a wave
             Pass p = base;
             p.wide = wide != 0;
             p.pcols = pc;
@@ -539,6 +581,40 @@ float time_pass(cbs_medium_s* m, int kind, const Slot<T>* dslot, const Pass& p, 
     return ms;
 }
 
+// Average time of the three middle passes run block by block.
+template <typename T>
+float time_middle(cbs_medium_s* m, const PassSet& ps, int blocks, const Slot<T>* dslot, hipStream_t st) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.f;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1.f;
+    }
+    const int lw = m->g.n[m->g.ndim - 1] / blocks;
+    auto once = [&]() {
+        for (int bl = 0; bl < blocks; ++bl)
+            for (int i = 1; i <= 3; ++i) {
+                const Pass& p = ps.p[i];
+                if (launch_pass<T>(p.kind, MODE_CBS, dslot, 1, m->g, p.axis, p.n, p.pcols, p.wide, p.variant, st,
+                                   bl * lw, lw) != hipSuccess)
+                    return false;
+            }
+        return true;
+    };
+    float ms = -1.f;
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) ok = once();
+    const int reps = 4;
+    ok = ok && hipEventRecord(a, st) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = once();
+    ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms /= reps;
+    else ms = -1.f;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
 template <typename T>
 cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T>* w, cx<T>* y, Ctl* ctl,
                     double* part, double* chunks, hipStream_t st) {
@@ -564,6 +640,20 @@ cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T
             }
         }
         ps.p[i] = pick;
+    }
+    // block count of the middle passes, timed as a chain with the plans above
+    ps.cblocks = 1;
+    if (ps.count == 5) {
+        const int pin = forced_cblocks();
+        float best = -1.f;
+        for (int blocks : {1, 2, 4, 8}) {
+            if ((pin > 0 && blocks != pin) || !cblocks_valid(m->g, ps, blocks)) continue;
+            const float t = time_middle<T>(m, ps, blocks, dslot, st);
+            if (t > 0.f && (best < 0.f || t < best)) {
+                best = t;
+                ps.cblocks = blocks;
+            }
+        }
     }
     const Pass& lp = ps.p[ps.count - 1];
     ps.nparts = (int)((m->g.ndim + 1) * (m->g.ncell / ((int64_t)lp.n * lp.pcols)));
@@ -629,10 +719,13 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
     std::lock_guard<std::mutex> mlk(m->tune_mu);
     if (!autotune_enabled()) {
         if (m->tuned64 && m->tuned32) return CBS_OK;
-        for (PassSet* ps : {&m->ps64, &m->ps32})
+        for (PassSet* ps : {&m->ps64, &m->ps32}) {
             for (int i = 0; i < ps->count; ++i)
                 if (ps->p[i].kind >= 1 && ps->p[i].kind <= 4)
                     ps->p[i].variant = std::max(0, forced_variant(ps->p[i].kind));
+            const int blocks = forced_cblocks();
+            ps->cblocks = (blocks > 0 && cblocks_valid(m->g, *ps, blocks)) ? blocks : 1;
+        }
         m->tuned64 = m->tuned32 = true;
         return CBS_OK;
     }
@@ -644,7 +737,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         if (done) continue;
         PassSet& ps = fp64 ? m->ps64 : m->ps32;
         const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_variant(4), forced_variant(1),
-                          forced_variant(2)};
+                          forced_variant(2), forced_cblocks()};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(key);
@@ -1302,7 +1395,8 @@ cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]) {
         out[4 * i + 0] = have ? ps.p[i].kind : -1;
         out[4 * i + 1] = have ? ps.p[i].n : 0;
         out[4 * i + 2] = have ? ps.p[i].pcols : 0;
-        out[4 * i + 3] = have ? ((ps.p[i].wide ? 1 : 0) | (ps.p[i].variant << 1)) : 0;
+        const int blocks = (have && ps.count == 5 && i >= 1 && i <= 3) ? ps.cblocks : 1;
+        out[4 * i + 3] = have ? ((ps.p[i].wide ? 1 : 0) | (ps.p[i].variant << 1) | (blocks << 4)) : 0;
     }
     return CBS_OK;
 }

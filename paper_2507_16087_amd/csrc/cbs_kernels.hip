@@ -2,29 +2,30 @@
 // on the staggered first-order system of App. B.1).
 //
 // One CBS iteration (eq. BornAlt: x <- x + nu B [(L+I)^{-1}(B x + y) - x]) on
-// an n0 x n1 x n2 grid with F = ndim + 1 complex fields runs as five passes
+// an n0 x n1 x n2 grid with F = ndim + 1 complex fields is a set of passes
 // over HBM, each a batch of 1-D FFTs along one axis:
-//   pass A  axis 2 (contiguous): w = B x + y fused into the load, forward FFT
+//   pass A  axis 2 (contiguous): w = B x + y formed on load, forward FFT
 //   pass B  axis 1 (strided)   : forward FFT                        (3-D only)
 //   pass C  axis 0 (strided)   : forward FFT, (L+I)^{-1} per wavevector with
 //                                all F fields in registers, inverse FFT
 //   pass D  axis 1 (strided)   : inverse FFT                        (3-D only)
-//   pass E  axis 2 (contiguous): inverse FFT, x += nu B (z - x) and the
-//                                |dx|^2, |x|^2 partial sums fused into the store
-// followed by a one-block-per-slot reduction that advances the iteration
-// counter and raises the slot's stop flag.  The same passes with a different
-// middle operator (i k S / sqrt(lam1 lam2)) and epilogue (r = y - D x / lam - z)
-// evaluate the scaled true residual y - (L+V) x used by iterative refinement.
+//   pass E  axis 2 (contiguous): inverse FFT, x += nu B (z - x) with the
+//                                |dx|^2, |x|^2 partial sums
+// In steady state E and the next iteration's A are one kernel (the fused
+// kind): the inverse transform runs its radices in reverse order, so the
+// registers it ends with are exactly the forward transform's first-stage
+// inputs.  A two-level reduction kernel then folds the partial sums in index
+// order, advances the iteration counter and raises the slot's stop flag.
+// The same passes with a different middle operator (i k S / sqrt(lam1 lam2))
+// and epilogue (r = y - D x / lam - z) evaluate the scaled true residual
+// y - (L+V) x used by iterative refinement.
 //
 // FFTs are Stockham radix-R stages (R in 2..16, including 3, 6, 12): every
-// thread owns whole butterflies, the first stage of a strided pass loads
-// straight from HBM (columns of P adjacent cells give coalesced row segments),
-// stages exchange through an LDS tile, and the last stage stores straight to
-// HBM in natural order.  Contiguous passes stage the P-pencil tile through LDS
-// with a fully coalesced copy so the fused prologue / epilogue read and write
-// whole cache lines.  The middle pass keeps the forward spectrum in registers
-// and starts the inverse transform from them (reversed radix order), so the
-// propagator costs no extra LDS or HBM traffic.
+// thread owns whole butterflies, the first stage loads straight from HBM and
+// the last stage stores straight to HBM in natural order, and stages exchange
+// through an LDS tile.  Strided passes map threads column-fastest (a tile of P
+// adjacent columns reads P-element row segments); contiguous passes map them
+// lane-fastest along each pencil, so loads and stores run along cache lines.
 #include "cbs_internal.h"
 
 #include <algorithm>
@@ -648,7 +649,7 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int G) {
 template <class P, int DIR, typename T>
 __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slots, Geom g, int axis,
                                                  int pcols, int ldp, int64_t es, int64_t ostride,
-                                                 int nlast_tiles, int skip_done, int xg) {
+                                                 int nlast_tiles, int skip_done, int xg, int l0) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Slot<T>& s = slots[blockIdx.z];
@@ -656,7 +657,7 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
-    cx<T>* __restrict__ w = s.w + (int64_t)blockIdx.y * g.ncell + (int64_t)(tile / nlast_tiles) * ostride +
+    cx<T>* __restrict__ w = s.w + (int64_t)blockIdx.y * g.ncell + (int64_t)(tile / nlast_tiles) * ostride + l0 +
                             (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
     cx<T> v[P::E];
@@ -689,7 +690,7 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 //   exchange shared by all fields; 2: two regions, fields in pairs.
 template <class P, int MODE, int VAR, typename T>
 __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols, int ldp,
-                                              int64_t es, int64_t ostride, int nlast_tiles, int xg) {
+                                              int64_t es, int64_t ostride, int nlast_tiles, int xg, int l0) {
     constexpr int NR = VAR == 1 ? 4 : (VAR == 2 ? 2 : 1);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -857,11 +858,11 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
 
     // tile: index io along the middle axis (3-D), columns along the last
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
-    cx<T>* wt = s.w + (int64_t)(tile / nlast_tiles) * ostride + (int64_t)(tile % nlast_tiles) * pcols;
+    cx<T>* wt = s.w + (int64_t)(tile / nlast_tiles) * ostride + l0 + (int64_t)(tile % nlast_tiles) * pcols;
     cx<T> v[4][E];
     __syncthreads();   // tables staged
     load(v, wt);
-    run(v, (int)(tile / nlast_tiles), (int)(tile % nlast_tiles) * pcols + col, wt);
+    run(v, (int)(tile / nlast_tiles), l0 + (int)(tile % nlast_tiles) * pcols + col, wt);
 }
 
 // ---------------------------------------------------------- reductions --
@@ -1110,7 +1111,7 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // 3 strided inverse, 4 axis-0 propagator.
 template <typename T, class P>
 static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis,
-                              int pcols, int variant, hipStream_t st) {
+                              int pcols, int variant, int l0, int lw, hipStream_t st) {
     const int N = P::N;
     // column tiles (strided and propagator passes) are padded by one element
     // per row unless variant bit 2 asks for the unpadded pitch
@@ -1156,7 +1157,10 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         // strided along `axis`; columns run along the last axis in groups of pcols
         int64_t es = 1;
         for (int d = axis + 1; d < g.ndim; ++d) es *= g.n[d];
-        const int nlast_tiles = g.n[last] / pcols;
+        // columns [l0, l0 + lw) of the last axis (lw = 0: all of it)
+        if (lw == 0) lw = g.n[last];
+        if (l0 < 0 || lw <= 0 || l0 + lw > g.n[last] || lw % pcols || l0 % pcols) return hipErrorInvalidValue;
+        const int nlast_tiles = lw / pcols;
         // the remaining ("other") axis: the one that is neither `axis` nor last
         int other = -1;
         for (int d = 0; d < g.ndim - 1; ++d)
@@ -1179,7 +1183,7 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
             if (lp > kMaxLdsBytes) return hipErrorInvalidConfiguration;
 #define PROP_LAUNCH(M, V)                                                                                     \
     hipLaunchKernelGGL((k_prop<P, M, V, T>), grid, block, lp, st, slots, g, pcols, ldp, es, ostride, nlast_tiles, \
-                       xg)
+                       xg, l0)
             if (mode == CBS) {
                 if (variant == 1) PROP_LAUNCH(CBS, 1);
                 else if (variant == 2) PROP_LAUNCH(CBS, 2);
@@ -1196,10 +1200,10 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
             const int skip = mode == CBS ? 1 : 0;
             if (kind == 2)
                 hipLaunchKernelGGL((k_strided<P, -1, T>), grid, block, lds, st, slots, g, axis, pcols, ldp, es,
-                                   ostride, nlast_tiles, skip, xg);
+                                   ostride, nlast_tiles, skip, xg, l0);
             else
                 hipLaunchKernelGGL((k_strided<P, 1, T>), grid, block, lds, st, slots, g, axis, pcols, ldp, es,
-                                   ostride, nlast_tiles, skip, xg);
+                                   ostride, nlast_tiles, skip, xg, l0);
         }
     }
     return hipGetLastError();
@@ -1207,10 +1211,10 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
 
 template <typename T>
 hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
-                       int pcols, bool wide, int variant, hipStream_t st) {
+                       int pcols, bool wide, int variant, hipStream_t st, int l0, int lw) {
 #define LAUNCH_CASE(N_, A, B, C, T_) \
     if (n == N_)                     \
-        return launch_plan<T, Plan<N_, A, B, C, T_>>(kind, mode, slots, nslots, g, axis, pcols, variant, st);
+        return launch_plan<T, Plan<N_, A, B, C, T_>>(kind, mode, slots, nslots, g, axis, pcols, variant, l0, lw, st);
     if (wide) { CBS_PLANS_WIDE(LAUNCH_CASE) }
     CBS_PLANS(LAUNCH_CASE)
 #undef LAUNCH_CASE
@@ -1218,9 +1222,9 @@ hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, con
 }
 
 template hipError_t launch_pass<float>(int, int, const Slot<float>*, int, const Geom&, int, int, int, bool, int,
-                                       hipStream_t);
+                                       hipStream_t, int, int);
 template hipError_t launch_pass<double>(int, int, const Slot<double>*, int, const Geom&, int, int, int, bool, int,
-                                        hipStream_t);
+                                        hipStream_t, int, int);
 
 template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st) {

@@ -122,12 +122,13 @@ class Medium:
     def pass_config(self, prec="fp64") -> list:
         """Pass plans of one iteration at this precision, in launch order (tuned
         by the first solve): kind, axis length, columns per work-group, wide
-        radix split, LDS variant (propagator only: 0 one tile reused field by
-        field, 1 one region per field, 2 fields in pairs)."""
+        radix split, variant, and the number of last-axis column blocks the
+        middle passes run in."""
         cfg = (C.c_int32 * 20)()
         L.check(L.lib().cbs_pass_config(self._h, PREC[prec], cfg), "cbs_pass_config")
         return [dict(kind=cfg[4 * i], n=cfg[4 * i + 1], cols=cfg[4 * i + 2],
-                     wide=cfg[4 * i + 3] & 1, variant=cfg[4 * i + 3] >> 1)
+                     wide=cfg[4 * i + 3] & 1, variant=(cfg[4 * i + 3] >> 1) & 7,
+                     blocks=cfg[4 * i + 3] >> 4)
                 for i in range(5) if cfg[4 * i] >= 0]
 
     def workspace_bytes(self, prec="fp64", batch=1) -> int:

@@ -176,21 +176,26 @@ def _plan(gm, prec, kind):
 @pytest.mark.parametrize("pin", [("CBS_PROP_VARIANT", 0), ("CBS_PROP_VARIANT", 1), ("CBS_PROP_VARIANT", 2),
                                  ("CBS_PROP_VARIANT", 4), ("CBS_PROP_VARIANT", 5), ("CBS_PROP_VARIANT", 6),
                                  ("CBS_LAST_VARIANT", 0), ("CBS_LAST_VARIANT", 1), ("CBS_LAST_VARIANT", 2),
-                                 ("CBS_STRIDED_VARIANT", 4)])
+                                 ("CBS_STRIDED_VARIANT", 4), ("CBS_COLUMN_BLOCKS", 1), ("CBS_COLUMN_BLOCKS", 2),
+                                 ("CBS_COLUMN_BLOCKS", 4), ("CBS_COLUMN_BLOCKS", 8)])
 @pytest.mark.parametrize("shape", [(48, 32), (16, 24, 32), (64, 8, 16), (256, 4, 8)])
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_pass_variants_match_oracle(orc, cbs, monkeypatch, pin, shape, adjoint):
     """Every pass variant the tuner may pick, pinned in turn, against the
     oracle: the propagator's LDS layouts (one tile reused field by field, one
     region per field, fields in pairs; each with or without row padding of
-    the column tile), the strided passes without row padding, and the
-    last-axis inverse pass's prefetch of x, y and the medium.  FP64 iterates
-    and the refined FP32 solve."""
+    the column tile), the strided passes without row padding, the last-axis
+    inverse pass's prefetch of x, y and the medium, and the middle passes
+    run in 1, 2, 4 or 8 column blocks.  FP64 iterates and the refined FP32
+    solve."""
     name, variant = pin
-    if name == "CBS_STRIDED_VARIANT" and len(shape) == 2:
-        pytest.skip("2-D grids have no strided pass")
+    if name in ("CBS_STRIDED_VARIANT", "CBS_COLUMN_BLOCKS") and len(shape) == 2:
+        pytest.skip("2-D grids have no strided passes")
+    if name == "CBS_COLUMN_BLOCKS" and shape[-1] // variant < 8:
+        pytest.skip("blocks narrower than 8 columns")
     monkeypatch.setenv(name, str(variant))
-    kind = {"CBS_PROP_VARIANT": 4, "CBS_LAST_VARIANT": 1, "CBS_STRIDED_VARIANT": 2}[name]
+    kind = {"CBS_PROP_VARIANT": 4, "CBS_LAST_VARIANT": 1, "CBS_STRIDED_VARIANT": 2, "CBS_COLUMN_BLOCKS": 4}[name]
+    key = "blocks" if name == "CBS_COLUMN_BLOCKS" else "variant"
     om, gm = _pair(orc, cbs, shape, pml=1, seed=5)
     F = len(shape) + 1
     s = np.zeros((F,) + shape, complex)
@@ -199,13 +204,13 @@ def test_pass_variants_match_oracle(orc, cbs, monkeypatch, pin, shape, adjoint):
     flat[1, 77] = 0.25
     xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=25, adjoint=adjoint)
     p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=0.0, max_iter=25, adjoint=adjoint)
-    assert _plan(gm, "fp64", kind)["variant"] == variant
+    assert _plan(gm, "fp64", kind)[key] == variant
     assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
     xs, _ = om.solve(om.source_hat(s), tol=1e-12, max_iter=100000, adjoint=adjoint)
     p, u, info = cbs.solve(gm, s[-1], s[:-1], tol=1e-7, prec="fp32_refined", inner_tol=1e-4,
                            adjoint=adjoint)
     assert info["converged"]
-    assert _plan(gm, "fp32_refined", kind)["variant"] == variant
+    assert _plan(gm, "fp32_refined", kind)[key] == variant
     assert _rel(p, xs[-1]) <= 1e-5 and _rel(u, xs[:-1]) <= 1e-5
 
 
