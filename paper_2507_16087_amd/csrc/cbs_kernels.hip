@@ -64,6 +64,33 @@ __device__ __forceinline__ cx<T> cinv_fast(cx<T> a) {
 template <typename T>
 __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
 
+// ------------------------------------------------------- global memory --
+// The solver's device pointers reach the kernels through the slot descriptor,
+// so the compiler cannot tell them from LDS or scratch and would use flat
+// memory instructions; flat accesses count against the LDS wait counter too,
+// so every LDS exchange of an FFT would also wait for all loads and stores in
+// flight.  The hot passes view their arrays through global-address-space
+// pointers instead.
+// (The host pass of the compiler parses these kernels too but emits no code
+// for them; there the qualifier is left out.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL __attribute__((address_space(1)))
+#else
+#define GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ GLOBAL T* gmem(T* p) {
+    return (GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const GLOBAL T* gmem(const T* p) {
+    return (const GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ T ldg(const GLOBAL T* p) {
+    return *p;
+}
+
 // ------------------------------------------------ compile-time twiddles --
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double taylor_sin(double x) {
@@ -499,17 +526,18 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
     cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tab_off);
     T* prof_l = reinterpret_cast<T*>(tw_l + N);
     {
-        const T* __restrict__ src = (f == last) ? s.gs[last] : s.gc[last];
+        const GLOBAL T* __restrict__ src = gmem((f == last) ? s.gs[last] : s.gc[last]);
+        const GLOBAL cx<T>* __restrict__ twg = gmem(s.tw[last]);
         for (int i = tid; i < N; i += blockDim.x) {
-            tw_l[i] = s.tw[last][i];
+            tw_l[i] = twg[i];
             prof_l[i] = src[i];
         }
     }
     __syncthreads();
     const cx<T>* tw = tw_l;
-    cx<T>* __restrict__ w = s.w + fbase;
-    cx<T>* __restrict__ x = s.x + fbase;
-    const cx<T>* __restrict__ y = s.y + fbase;
+    GLOBAL cx<T>* __restrict__ w = gmem(s.w) + fbase;
+    GLOBAL cx<T>* __restrict__ x = gmem(s.x) + fbase;
+    const GLOBAL cx<T>* __restrict__ y = gmem(s.y) + fbase;
 
     // per-pencil part of the layer rate for this field's row
     int ix[3];
@@ -520,11 +548,11 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
         ix[0] = pencil;
     }
     T colsum = 0;
-    for (int d = 0; d < last; ++d) colsum += (d == f) ? s.gs[d][ix[d]] : s.gc[d][ix[d]];
+    for (int d = 0; d < last; ++d) colsum += gmem((d == f) ? s.gs[d] : s.gc[d])[ix[d]];
     const T* lastprof = prof_l;
     const bool urow = f < D;
-    const T* __restrict__ rb = s.rhobar + (urow ? fbase : 0) + pl;
-    const cx<T>* __restrict__ qv = s.q + tile0 + pl;
+    const GLOBAL T* __restrict__ rb = gmem(s.rhobar) + (urow ? fbase : 0) + pl;
+    const GLOBAL cx<T>* __restrict__ qv = gmem(s.q) + tile0 + pl;
     const T are = urow ? s.a1re : s.a2re;
     const T aim = s.adjoint ? -(urow ? s.a1im : s.a2im) : (urow ? s.a1im : s.a2im);
     const T il = urow ? s.inv_lam1 : s.inv_lam2;
@@ -592,7 +620,7 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                 const int n = out_index<P, 1>(lane, b, r);
                 const int e = b * RL + r;
                 const cx<T> z = v[e];
-                const cx<T> xv = PF ? xp[PF ? e : 0] : x[pl + n];
+                const cx<T> xv = PF ? xp[PF ? e : 0] : ldg(x + pl + n);
                 const cx<T> dd = PF ? diag_m(n, mp[PF ? e : 0]) : diag(n);
                 if constexpr (MODE == CBS) {
                     const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
@@ -601,9 +629,9 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                     x[pl + n] = xn;
                     acc0 += (double)norm2(dxv);
                     acc1 += (double)norm2(xv);
-                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : y[pl + n]);
+                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : ldg(y + pl + n));
                 } else {
-                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : y[pl + n];
+                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : ldg(y + pl + n);
                     const cx<T> rr = yv - rmul(il, cmul(dd, xv)) - z;
                     w[pl + n] = rr;
                     acc0 += (double)norm2(rr);
@@ -615,8 +643,8 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
         block_sum2(acc0, acc1, red);
         if (tid == 0) {
             const int64_t part = (int64_t)f * gridDim.x + blockIdx.x;
-            s.partials[2 * part] = acc0;
-            s.partials[2 * part + 1] = acc1;
+            gmem(s.partials)[2 * part] = acc0;
+            gmem(s.partials)[2 * part + 1] = acc1;
         }
         if constexpr (KIND == LAST) return;
         __syncthreads();
@@ -657,7 +685,7 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
-    cx<T>* __restrict__ w = s.w + (int64_t)blockIdx.y * g.ncell + (int64_t)(tile / nlast_tiles) * ostride + l0 +
+    GLOBAL cx<T>* __restrict__ w = gmem(s.w) + (int64_t)blockIdx.y * g.ncell + (int64_t)(tile / nlast_tiles) * ostride + l0 +
                             (int64_t)(tile % nlast_tiles) * pcols;
     const uint32_t es32 = (uint32_t)es;
     cx<T> v[P::E];
@@ -669,7 +697,7 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
             v[b * Seq<P, DIR>::r(0) + r] = w[(uint32_t)col + (uint32_t)in_index<P, DIR>(lane, b, r) * es32];
     // twiddles in LDS after the tile (first used after the first stage's barrier)
     cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tile_bytes<T>((size_t)P::N * ldp));
-    for (int i = tid; i < P::N; i += blockDim.x) tw_l[i] = s.tw[axis][i];
+    for (int i = tid; i < P::N; i += blockDim.x) tw_l[i] = gmem(s.tw[axis])[i];
     if constexpr (P::S == 1) __syncthreads();
     fft_regs<P, DIR>(v, lds, ldp, col, lane, tw_l);
     constexpr int Rl = Seq<P, DIR>::r(P::S - 1);
@@ -707,9 +735,9 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     cx<T>* g0_l = tw_l + N;
     T* k0_l = reinterpret_cast<T*>(g0_l + N);
     for (int i = tid; i < N; i += blockDim.x) {
-        tw_l[i] = s.tw[0][i];
-        k0_l[i] = s.kv[0][i];
-        g0_l[i] = rmul(s.kv[0][i], s.sh[0][i]);
+        tw_l[i] = gmem(s.tw[0])[i];
+        k0_l[i] = gmem(s.kv[0])[i];
+        g0_l[i] = rmul(gmem(s.kv[0])[i], gmem(s.sh[0])[i]);
     }
     const cx<T>* tw = tw_l;
     using QF = Seq<P, -1>;
@@ -719,11 +747,11 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     constexpr int RL = QI::r(P::S - 1);
 
     // first-stage inputs of every field of one tile, straight from HBM
-    auto load = [&](cx<T> (&v)[4][E], const cx<T>* __restrict__ wt) {
+    auto load = [&](cx<T> (&v)[4][E], const GLOBAL cx<T>* __restrict__ wt) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             if (f < F) {
-                const cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
+                const GLOBAL cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
 #pragma unroll
                 for (int b = 0; b < N / (R0 * P::TPC); ++b)
 #pragma unroll
@@ -735,18 +763,18 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
 
     // transforms, operator and stores of one tile whose registers are loaded;
     // the LDS regions must be free on entry
-    auto run = [&](cx<T> (&v)[4][E], int io, int il, cx<T>* __restrict__ wt) {
+    auto run = [&](cx<T> (&v)[4][E], int io, int il, GLOBAL cx<T>* __restrict__ wt) {
         // wavevector components of this column (axes 1.., FFT order)
         T kc[2];
         cx<T> gc[2];   // k S for the column axes
         if (D == 3) {
-            kc[0] = s.kv[1][io];
-            gc[0] = rmul(kc[0], s.sh[1][io]);
-            kc[1] = s.kv[2][il];
-            gc[1] = rmul(kc[1], s.sh[2][il]);
+            kc[0] = gmem(s.kv[1])[io];
+            gc[0] = rmul(kc[0], gmem(s.sh[1])[io]);
+            kc[1] = gmem(s.kv[2])[il];
+            gc[1] = rmul(kc[1], gmem(s.sh[2])[il]);
         } else {
-            kc[0] = s.kv[1][il];
-            gc[0] = rmul(kc[0], s.sh[1][il]);
+            kc[0] = gmem(s.kv[1])[il];
+            gc[0] = rmul(kc[0], gmem(s.sh[1])[il]);
             kc[1] = 0;
             gc[1] = {0, 0};
         }
@@ -846,7 +874,7 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
                     __syncthreads();
                     fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
                 }
-                cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
+                GLOBAL cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
 #pragma unroll
                 for (int b = 0; b < N / (RL * P::TPC); ++b)
 #pragma unroll
@@ -858,7 +886,7 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
 
     // tile: index io along the middle axis (3-D), columns along the last
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
-    cx<T>* wt = s.w + (int64_t)(tile / nlast_tiles) * ostride + l0 + (int64_t)(tile % nlast_tiles) * pcols;
+    GLOBAL cx<T>* wt = gmem(s.w) + (int64_t)(tile / nlast_tiles) * ostride + l0 + (int64_t)(tile % nlast_tiles) * pcols;
     cx<T> v[4][E];
     __syncthreads();   // tables staged
     load(v, wt);
