@@ -41,7 +41,8 @@
  *  - Errors: status codes only.  On CBS_E_* outputs are untouched.  On
  *    CBS_NOT_CONVERGED the outputs hold the last iterate.
  *  - Threading: a medium is immutable after creation except through
- *    cbs_set_scalars; concurrent calls on one medium must use different
+ *    cbs_set_scalars, which must not overlap any other call on the same
+ *    medium; concurrent calls on one medium must use different
  *    workspaces and streams (the first solves tune the pass plans once,
  *    under a lock).  Per-pass timing (cbs_pass_timing*) is a measurement aid
  *    for one thread at a time.
@@ -226,7 +227,8 @@ cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
  * Environment: CBS_AUTOTUNE=0 keeps the defaults; CBS_PROP_VARIANT (0, 1, 2,
  * 4, 5, 6), CBS_LAST_VARIANT (0, 1, 2), CBS_STRIDED_VARIANT (0, 4) and
  * CBS_COLUMN_BLOCKS (1, 2, 4, 8) pin a choice, tuned or not.  Configurations
- * needing more than 160 KiB of LDS are never launched. */
+ * needing more than 160 KiB of LDS are never launched.  CBS_E_INVALID for a
+ * null argument or a prec other than CBS_FP64 and CBS_FP32_REFINED. */
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
 
 /* Totals so far: ms[g * 6 + k] and launches[g * 6 + k] for group g (0 FP32

@@ -784,10 +784,6 @@ cbs_status validate_grid(const cbs_grid* g) {
     return CBS_OK;
 }
 
-struct StreamGuard {
-    hipStream_t s;
-};
-
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -1389,6 +1385,7 @@ cbs_status cbs_gradient(cbs_medium m, const void* s_p, const void* s_u, const vo
 
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]) {
     if (!m || !out) return CBS_E_INVALID;
+    if (prec != CBS_FP64 && prec != CBS_FP32_REFINED) return CBS_E_INVALID;
     const PassSet& ps = prec == CBS_FP64 ? m->ps64 : m->ps32;
     for (int i = 0; i < 5; ++i) {
         const bool have = i < ps.count;
@@ -1429,7 +1426,6 @@ cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18
     return CBS_OK;
 }
 
-// batched slots: implemented in cbs_batch.cpp
 }  // extern "C"
 
 // =================================================== batched slots ======

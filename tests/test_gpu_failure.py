@@ -77,3 +77,24 @@ def test_admission_queues_when_budget_is_tight(cbs):
     out = srv.run(reqs)
     assert out["converged"] == 4
     assert out["max_concurrency"] == 1
+
+
+def test_invalid_arguments_on_a_medium(cbs):
+    """Argument checks that need a live medium: unknown precision, an empty
+    batch, a non-positive scale; each returns CBS_E_INVALID and changes
+    nothing."""
+    import ctypes as C
+    from paper_2507_16087_amd import _lib
+    pr = _prob(8)
+    m = cbs.Medium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=2)
+    L = _lib.lib()
+    cfg = (C.c_int32 * 20)()
+    nb = C.c_size_t(0)
+    assert L.cbs_pass_config(m._h, 7, cfg) == _lib.CBS_E_INVALID
+    assert L.cbs_workspace_bytes(m._h, 7, 1, C.byref(nb)) == _lib.CBS_E_INVALID
+    assert L.cbs_workspace_bytes(m._h, 0, 0, C.byref(nb)) == _lib.CBS_E_INVALID
+    before = m.scalars()
+    a1, a2 = before["a1"], before["a2"]
+    bad = (C.c_double * 6)(a1.real, a1.imag, a2.real, a2.imag, -1.0, before["lam2"])
+    assert L.cbs_set_scalars(m._h, bad) == _lib.CBS_E_INVALID
+    assert m.scalars() == before
