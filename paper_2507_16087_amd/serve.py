@@ -43,6 +43,7 @@ class Result:
     outer: int = 0
     rel_residual: float = -1.0
     converged: bool = False
+    error: Optional[str] = None     # set when planning or the solve failed
     p: Optional[np.ndarray] = None
 
     @property
@@ -72,11 +73,16 @@ class _Pool:
                 item = None
             while item is not None:
                 rid, medium, sp = item
-                slot = self.batch.submit(medium, sp, tol=self.server.tol,
-                                         inner_tol=self.server.inner_tol)
-                assert slot >= 0, "admission promised a free slot"
-                self.slot_rid[slot] = rid
-                self.server._mark(rid, "submitted")
+                try:
+                    slot = self.batch.submit(medium, sp, tol=self.server.tol,
+                                             inner_tol=self.server.inner_tol)
+                except solver.L.CbsError as e:
+                    self.server._fail(rid, self, f"submit: {e}")
+                    slot = None
+                if slot is not None:
+                    assert slot >= 0, "admission promised a free slot"
+                    self.slot_rid[slot] = rid
+                    self.server._mark(rid, "submitted")
                 try:
                     item = self.inbox.get_nowait()
                 except queue.Empty:
@@ -86,8 +92,12 @@ class _Pool:
                     return
                 continue
             for slot in self.batch.step(self.server.step_iters):
-                p, _, info = self.batch.retire(slot)
                 rid = self.slot_rid.pop(slot)
+                try:
+                    p, _, info = self.batch.retire(slot)
+                except solver.L.CbsError as e:    # e.g. a diverged solve
+                    self.server._fail(rid, self, f"solve: {e}")
+                    continue
                 self.server._finish(rid, self, p, info)
 
 
@@ -119,12 +129,14 @@ class Server:
         with self.lock:
             setattr(self.results[rid], what, time.perf_counter())
 
-    def _finish(self, rid, pool, p, info):
+    def _finish(self, rid, pool, p, info, error=None):
         with self.cv:
             r = self.results[rid]
             r.done = time.perf_counter()
-            r.iterations, r.outer = info["iterations"], info["outer"]
-            r.rel_residual, r.converged = info["rel_residual"], info["converged"]
+            if error is None:
+                r.iterations, r.outer = info["iterations"], info["outer"]
+                r.rel_residual, r.converged = info["rel_residual"], info["converged"]
+            r.error = error
             if self.keep_fields:
                 r.p = p
             pool.reserved -= 1
@@ -132,6 +144,11 @@ class Server:
             self.active -= 1
             self.timeline.append((r.done, self.active))
             self.cv.notify_all()
+
+    def _fail(self, rid, pool, error: str):
+        """Close a request that could not be planned or solved; its slot
+        reservation and HBM share are released like a finished one's."""
+        self._finish(rid, pool, None, None, error=error)
 
     @staticmethod
     def _medium_bytes(shape):
@@ -176,7 +193,11 @@ class Server:
             self.results[req.rid].admitted = time.perf_counter()
 
         def plan():
-            m = solver.Medium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
+            try:
+                m = solver.Medium(pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, pml=pr.pml_cells)
+            except (solver.L.CbsError, ValueError) as e:
+                self._fail(req.rid, pool, f"plan: {e}")
+                return
             pool.inbox.put((req.rid, m, pr.dense_source().ravel()))
 
         self.planner.submit(plan)
@@ -202,6 +223,9 @@ class Server:
                 if i == len(reqs) and not pending and all(r.done > 0 for r in self.results.values()):
                     break
                 self.cv.wait(timeout=0.002)
+            dead = [p for p in self.pools.values() if not p.thread.is_alive()]
+            if dead:
+                raise RuntimeError(f"serving thread of pool {dead[0].shape} ended unexpectedly")
         for p in self.pools.values():
             p.stop = True
         for p in self.pools.values():
@@ -213,4 +237,5 @@ class Server:
         return dict(results=res, p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), solves_per_s=len(res) / span,
                     wall_s=span, max_concurrency=max((a for _, a in self.timeline), default=0),
-                    converged=sum(r.converged for r in res))
+                    converged=sum(r.converged for r in res),
+                    failed=sum(r.error is not None for r in res))

@@ -328,8 +328,9 @@ class Batch:
             kind = L.CBS_PTR_HOST
         info = L.SolveInfo()
         st = L.lib().cbs_batch_retire(self._h, int(slot), _ptr(p), _ptr(u), kind, C.byref(info))
+        if st in (L.CBS_OK, L.CBS_NOT_CONVERGED, L.CBS_E_DIVERGED):   # the slot is free again
+            self.media.pop(int(slot), None)
         L.check(st, "cbs_batch_retire", (L.CBS_OK, L.CBS_NOT_CONVERGED))
-        self.media.pop(int(slot), None)
         d = info.as_dict()
         d["converged"] = st == L.CBS_OK
         p = p.reshape(self.shape)

@@ -98,3 +98,20 @@ def test_invalid_arguments_on_a_medium(cbs):
     bad = (C.c_double * 6)(a1.real, a1.imag, a2.real, a2.imag, -1.0, before["lam2"])
     assert L.cbs_set_scalars(m._h, bad) == _lib.CBS_E_INVALID
     assert m.scalars() == before
+
+
+def test_server_reports_a_request_it_cannot_plan(cbs):
+    """A request whose medium is rejected (a negative sound speed) is closed
+    with an error; the requests around it still complete and the run ends."""
+    from paper_2507_16087_amd.serve import Server
+    reqs = []
+    for i in range(3):
+        pr = _prob(24)
+        if i == 1:
+            pr.c = np.array(pr.c, copy=True)
+            pr.c.flat[0] = -1.0
+        reqs.append(W.Request(i, 0.0, pr))
+    out = Server(tol=1e-6, slots_per_pool=2).run(reqs)
+    assert out["converged"] == 2 and out["failed"] == 1
+    bad = out["results"][1]
+    assert bad.error is not None and "plan" in bad.error and not bad.converged
