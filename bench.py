@@ -14,6 +14,8 @@ Prints one JSON line.  Fields beyond the driver contract:
   passes           -- per-pass average duration (HIP events) and achieved GB/s
   roofline         -- dominant kernel against the 8 TB/s HBM peak
   cpu_baseline     -- the FP64 oracle on a bounded sample of the same workload
+  pressure_rel_diff_refined_vs_fp64 -- relative L2 distance of the two solves'
+                      pressure fields (both stopped at the same FP64 residual)
 """
 from __future__ import annotations
 
@@ -274,11 +276,15 @@ def main():
         ws64 = m.workspace("fp64")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, i64 = solver.solve(m, sp, tol=args.tol, prec="fp64", check_every=args.check_every,
-                                 stop_rule=_lib.CBS_STOP_RESIDUAL, workspace=ws64, max_iter=200000)
+        p64, _, i64 = solver.solve(m, sp, tol=args.tol, prec="fp64", check_every=args.check_every,
+                                   stop_rule=_lib.CBS_STOP_RESIDUAL, workspace=ws64, max_iter=200000)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
-        log(f"fp64: {i64['iterations']} it, res {i64['rel_residual']:.2e}, {t64:.2f} s")
+        # the two pressure fields, each converged to the same residual tolerance
+        diff = float(torch.linalg.vector_norm(p - p64) / torch.linalg.vector_norm(p64))
+        log(f"fp64: {i64['iterations']} it, res {i64['rel_residual']:.2e}, {t64:.2f} s; "
+            f"|p32 - p64| / |p64| = {diff:.2e}")
+        out["pressure_rel_diff_refined_vs_fp64"] = diff
         out["time_to_tol_ms"]["fp64_plain"] = round(t64 * 1e3, 2)
         out["iterations"]["fp64_plain"] = i64["iterations"]
         out["final_residual"]["fp64_plain"] = i64["rel_residual"]

@@ -64,7 +64,7 @@ def _grads(inv, data, spec):
     alpha = torch.tensor(pr.alpha, device="cuda", requires_grad=True)
     J = _misfit(inv, data, spec, c, rho, alpha)
     J.backward()
-    return float(J), [t.grad.cpu().numpy() for t in (c, rho, alpha)]
+    return J.detach().item(), [t.grad.cpu().numpy() for t in (c, rho, alpha)]
 
 
 def _oracle_grads(orc, inv, data):
