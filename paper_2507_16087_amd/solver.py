@@ -98,11 +98,14 @@ class Medium:
         L.check(L.lib().cbs_create_medium(C.byref(g), *[_ptr(a) for a in arrs], kind, sp,
                                           C.byref(h)), "cbs_create_medium")
         self._h = h
+        # held here so that the handle can be released during interpreter
+        # shutdown, when module globals may already be gone
+        self._destroy = L.lib().cbs_destroy_medium
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            L.lib().cbs_destroy_medium(h)
+            self._destroy(h)
             self._h = None
 
     @property
@@ -280,12 +283,13 @@ class Batch:
                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)),
                 "cbs_batch_create")
         self._h = h
+        self._destroy = L.lib().cbs_batch_destroy
         self.media = {}
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            L.lib().cbs_batch_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def submit(self, m: Medium, s_p, s_u=None, *, tol=1e-5, max_iter=200000, inner_tol=0.0,
