@@ -226,7 +226,11 @@ cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
  * candidate plans and block counts on its workspace and keeps the fastest.
  * Environment: CBS_AUTOTUNE=0 keeps the defaults; CBS_PROP_VARIANT (0, 1, 2,
  * 4, 5, 6), CBS_LAST_VARIANT (0, 1, 2), CBS_STRIDED_VARIANT (0, 4) and
- * CBS_COLUMN_BLOCKS (1, 2, 4, 8) pin a choice, tuned or not.  Configurations
+ * CBS_COLUMN_BLOCKS (1, 2, 4, 8) pin a choice, tuned or not; CBS_TUNE_FILE
+ * names a text file that keeps tuned sets across processes (one line per
+ * device architecture, shape, precision and pins; read before tuning, a
+ * newly tuned set appended; lines that do not fit their shape are ignored).
+ * Configurations
  * needing more than 160 KiB of LDS are never launched.  CBS_E_INVALID for a
  * null argument or a prec other than CBS_FP64 and CBS_FP32_REFINED. */
 cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);

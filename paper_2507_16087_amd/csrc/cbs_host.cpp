@@ -9,7 +9,10 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <cstdio>
 #include <new>
+#include <sstream>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -711,6 +714,107 @@ bool autotune_enabled() {
     return !(e && e[0] == '0');
 }
 
+// ------------------------------------------------------- tune file --
+// CBS_TUNE_FILE names a text file that keeps tuned pass sets across
+// processes, one line per (device architecture, shape, precision, pins):
+//   cbs-tune-v1 <arch> <ndim> <n0> <n1> <n2> <fp64> <4 pins> <count> <cblocks>
+//               then <kind> <axis> <n> <pcols> <wide> <variant> per pass.
+// A line is used only if it describes a valid set for the shape; a process
+// that tunes a key the file lacks appends its line.  Unset: nothing is read
+// or written.
+const char* tune_file() {
+    const char* e = std::getenv("CBS_TUNE_FILE");
+    return (e && e[0]) ? e : nullptr;
+}
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');   // feature suffixes do not change the plans
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string tune_prefix(const std::string& arch, const TuneKey& k) {
+    std::ostringstream o;
+    o << "cbs-tune-v1 " << arch << ' ' << k.ndim << ' ' << k.n0 << ' ' << k.n1 << ' ' << k.n2 << ' ' << k.fp64
+      << ' ' << k.prop_variant << ' ' << k.last_variant << ' ' << k.strided_variant << ' ' << k.cblocks;
+    return o.str();
+}
+
+// A pass set read from the file must match the shape's pass sequence and
+// stay inside what the tuner itself could have chosen.
+bool plausible(const Geom& g, const PassSet& def, const PassSet& ps) {
+    if (ps.count != def.count) return false;
+    const int last = g.ndim - 1;
+    for (int i = 0; i < ps.count; ++i) {
+        const Pass &p = ps.p[i], &d = def.p[i];
+        if (p.kind != d.kind || p.axis != d.axis || p.n != d.n) return false;
+        if (p.wide && !plan_has_wide(p.n)) return false;
+        const int tpc = plan_tpc(p.n, p.wide);
+        if (p.pcols < 1 || (p.pcols & (p.pcols - 1)) || tpc <= 0 || p.pcols * tpc > 256) return false;
+        const int64_t total = (p.kind == 0 || p.kind == 1) ? g.ncell / g.n[last] : g.n[last];
+        if (total % p.pcols) return false;
+        const std::vector<int> vs = variants_of(p.kind);
+        if (std::find(vs.begin(), vs.end(), p.variant) == vs.end()) return false;
+    }
+    return ps.cblocks == 1 || ((ps.cblocks == 2 || ps.cblocks == 4 || ps.cblocks == 8) && cblocks_valid(g, ps, ps.cblocks));
+}
+
+bool tune_file_lookup(const Geom& g, const TuneKey& key, const PassSet& def, PassSet* out) {
+    const char* path = tune_file();
+    if (!path) return false;
+    const std::string arch = device_arch();
+    if (arch.empty()) return false;
+    const std::string prefix = tune_prefix(arch, key) + ' ';
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char buf[1024];
+    while (!found && std::fgets(buf, sizeof buf, f)) {
+        const std::string line(buf);
+        if (line.compare(0, prefix.size(), prefix) != 0) continue;
+        std::istringstream in(line.substr(prefix.size()));
+        PassSet ps{};
+        if (!(in >> ps.count >> ps.cblocks) || ps.count < 1 || ps.count > 5) continue;
+        bool ok = true;
+        for (int i = 0; i < ps.count && ok; ++i) {
+            Pass& p = ps.p[i];
+            int wide = 0;
+            ok = static_cast<bool>(in >> p.kind >> p.axis >> p.n >> p.pcols >> wide >> p.variant);
+            p.wide = wide != 0;
+        }
+        if (!ok || !plausible(g, def, ps)) continue;
+        const Pass& lp = ps.p[ps.count - 1];
+        ps.nparts = (int)((g.ndim + 1) * (g.ncell / ((int64_t)lp.n * lp.pcols)));
+        *out = ps;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_file_append(const TuneKey& key, const PassSet& ps) {
+    const char* path = tune_file();
+    if (!path) return;
+    const std::string arch = device_arch();
+    if (arch.empty()) return;
+    std::ostringstream o;
+    o << tune_prefix(arch, key) << ' ' << ps.count << ' ' << ps.cblocks;
+    for (int i = 0; i < ps.count; ++i) {
+        const Pass& p = ps.p[i];
+        o << ' ' << p.kind << ' ' << p.axis << ' ' << p.n << ' ' << p.pcols << ' ' << (p.wide ? 1 : 0) << ' '
+          << p.variant;
+    }
+    o << '\n';
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;   // the file is an optimisation: a failed write changes nothing else
+    const std::string line = o.str();
+    (void)std::fwrite(line.data(), 1, line.size(), f);
+    std::fclose(f);
+}
+
 // Tune the pass sets this precision uses, on the caller's workspace (its
 // contents are scratch here), or take them from the process cache.
 cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
@@ -741,6 +845,11 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(key);
+            if (it == g_tune_cache.end()) {
+                PassSet from_file;
+                if (tune_file_lookup(g, key, make_passes(g, fp64 != 0), &from_file))
+                    it = g_tune_cache.emplace(key, from_file).first;
+            }
             if (it != g_tune_cache.end()) {
                 ps = it->second;
                 done = true;
@@ -762,6 +871,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         done = true;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = ps;
+        tune_file_append(key, ps);
     }
     return CBS_OK;
 }
