@@ -2,6 +2,7 @@
 // preprocessing), workspace layout, iteration drivers (plain FP64 and FP32
 // with FP64 iterative refinement), and the C ABI of include/cbs.h.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -13,6 +14,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -177,46 +179,100 @@ Circle from3(double ax, double ay, double bx, double by, double cx_, double cy_)
     return {ax + ox, ay + oy, std::hypot(ox, oy)};
 }
 
-// Smallest circle enclosing the points (Welzl's incremental algorithm).  An
-// exact pre-filter first drops points strictly inside the octagon spanned by
-// the extreme points in eight directions: such points are interior to the
-// convex hull and cannot lie on the minimum enclosing circle.
+// Run body(lo, hi) over [0, n) in contiguous chunks, one per host thread (at
+// most 16), the first on the calling thread.  Chunks are returned in order by
+// the caller's own bookkeeping, so results do not depend on the thread count.
+template <class F>
+void parallel_chunks(int64_t n, int nchunks, F&& body) {
+    std::vector<std::thread> pool;
+    for (int c = 1; c < nchunks; ++c)
+        pool.emplace_back([&, c] { body(c, n * c / nchunks, n * (c + 1) / nchunks); });
+    body(0, 0, n / nchunks);
+    for (std::thread& t : pool) t.join();
+}
+
+int plan_threads(int64_t n) {
+    if (n < (1 << 16)) return 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::min<unsigned>(16, std::max(1u, hw));
+}
+
+// Smallest circle enclosing the points (Welzl's incremental algorithm).  A
+// pre-filter first drops the points that cannot lie on the circle: those
+// strictly inside the octagon spanned by the extreme points in eight
+// directions (interior to the convex hull), copies of an octagon vertex (the
+// vertex itself is kept once), and points exactly on an octagon edge strictly
+// between its ends (on a chord of the enclosing disk, hence inside it).  The
+// last two matter for media with many equal values (a water background puts
+// millions of cells on one point) or values on a line (every cell outside
+// the absorbing layer has a purely imaginary velocity diagonal).  The scans
+// run on host threads; ties and the order of the kept points are those of a
+// serial scan.
 Circle min_circle(const std::vector<cd>& pts) {
     const size_t n = pts.size();
     if (n == 0) return {0, 0, 0};
     const double dirs[8][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
+    const int nt = plan_threads((int64_t)n);
+    std::vector<std::array<size_t, 8>> cext(nt);
+    std::vector<std::array<double, 8>> cbest(nt);
+    parallel_chunks((int64_t)n, nt, [&](int c, int64_t lo, int64_t hi) {
+        std::array<size_t, 8>& ext = cext[c];
+        std::array<double, 8>& best = cbest[c];
+        ext.fill(0);
+        best.fill(-INFINITY);
+        for (int64_t i = lo; i < hi; ++i)
+            for (int d = 0; d < 8; ++d) {
+                const double v = pts[i].real() * dirs[d][0] + pts[i].imag() * dirs[d][1];
+                if (v > best[d]) {
+                    best[d] = v;
+                    ext[d] = (size_t)i;
+                }
+            }
+    });
     size_t ext[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double best[8];
     for (int d = 0; d < 8; ++d) best[d] = -INFINITY;
-    for (size_t i = 0; i < n; ++i)
-        for (int d = 0; d < 8; ++d) {
-            const double v = pts[i].real() * dirs[d][0] + pts[i].imag() * dirs[d][1];
-            if (v > best[d]) {
-                best[d] = v;
-                ext[d] = i;
+    for (int c = 0; c < nt; ++c)   // chunk order: the first maximum wins, as in one scan
+        for (int d = 0; d < 8; ++d)
+            if (cbest[c][d] > best[d]) {
+                best[d] = cbest[c][d];
+                ext[d] = cext[c][d];
             }
-        }
     std::vector<cd> poly;
     for (int d = 0; d < 8; ++d) {
         const cd p = pts[ext[d]];
         if (poly.empty() || std::abs(poly.back() - p) > 0) poly.push_back(p);
     }
     while (poly.size() > 1 && std::abs(poly.front() - poly.back()) == 0) poly.pop_back();
-    std::vector<cd> keep;
-    keep.reserve(1024);
     const size_t m = poly.size();
-    for (size_t i = 0; i < n; ++i) {
-        bool inside = m >= 3;
-        for (size_t e = 0; e < m && inside; ++e) {
-            const cd a = poly[e], b = poly[(e + 1) % m];
-            const double cr = (b.real() - a.real()) * (pts[i].imag() - a.imag()) -
-                              (b.imag() - a.imag()) * (pts[i].real() - a.real());
-            // counter-clockwise octagon: interior points are strictly left of every edge
-            const double scale = std::abs(b - a) * (std::abs(pts[i] - a) + 1e-300);
-            if (!(cr > 1e-9 * scale)) inside = false;
+    std::vector<std::vector<cd>> ckeep(nt);
+    parallel_chunks((int64_t)n, nt, [&](int c, int64_t lo, int64_t hi) {
+        std::vector<cd>& keep = ckeep[c];
+        for (int64_t i = lo; i < hi; ++i) {
+            const cd p = pts[i];
+            bool inside = m >= 3, drop = false;
+            for (size_t e = 0; e < m && !drop; ++e) {
+                const cd a = poly[e], b = poly[(e + 1) % m];
+                if (p == a) {
+                    drop = true;   // a vertex value: the vertex is kept below
+                    break;
+                }
+                const double ex = b.real() - a.real(), ey = b.imag() - a.imag();
+                const double px = p.real() - a.real(), py = p.imag() - a.imag();
+                const double cr = ex * py - ey * px;
+                if (cr == 0.0) {
+                    const double t = ex * px + ey * py, len2 = ex * ex + ey * ey;
+                    if (t > 0.0 && t < len2) drop = true;   // on the edge, between its ends
+                }
+                // counter-clockwise octagon: interior points are strictly left of
+                // every edge, by a relative margin of 1e-9
+                if (!(cr > 0.0 && cr * cr > 1e-18 * (ex * ex + ey * ey) * (px * px + py * py))) inside = false;
+            }
+            if (!drop && !inside) keep.push_back(p);
         }
-        if (!inside) keep.push_back(pts[i]);
-    }
+    });
+    std::vector<cd> keep(poly.begin(), poly.end());
+    for (const std::vector<cd>& k : ckeep) keep.insert(keep.end(), k.begin(), k.end());
     // deterministic shuffle
     uint64_t s = 0x2545F4914F6CDD1Dull;
     for (size_t i = keep.size(); i > 1; --i) {
@@ -965,28 +1021,31 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
     std::vector<cd> Du((size_t)D * N), Dp(N);
     int64_t stride[3] = {1, 1, 1};
     for (int d = D - 2; d >= 0; --d) stride[d] = stride[d + 1] * g.n[d + 1];
-    for (int64_t i = 0; i < N; ++i) {
-        int ix[3] = {0, 0, 0};
-        int64_t r = i;
-        for (int d = D - 1; d >= 0; --d) {
-            ix[d] = (int)(r % g.n[d]);
-            r /= g.n[d];
+    const int nt = plan_threads(N);
+    parallel_chunks(N, nt, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            int ix[3] = {0, 0, 0};
+            int64_t r = i;
+            for (int d = D - 1; d >= 0; --d) {
+                ix[d] = (int)(r % g.n[d]);
+                r /= g.n[d];
+            }
+            const double cc = hc[i];
+            q[i] = cd(1.0, -2.0 * ha[i] * cc / w) / (hr[i] * cc * cc);
+            double gsum = 0.0;
+            for (int d = 0; d < D; ++d) gsum += prof_c[d][ix[d]];
+            const double gam = m->gmax * gsum;
+            Dp[i] = cd(gam, w) * q[i];
+            for (int e = 0; e < D; ++e) {
+                const int64_t nb = (ix[e] + 1 < g.n[e]) ? i + stride[e] : i - (int64_t)(g.n[e] - 1) * stride[e];
+                const double rbar = grid->collocated ? hr[i] : 0.5 * (hr[i] + hr[nb]);
+                rb[(size_t)e * N + i] = rbar;
+                double gs = 0.0;
+                for (int d = 0; d < D; ++d) gs += (d == e) ? prof_s[d][ix[d]] : prof_c[d][ix[d]];
+                Du[(size_t)e * N + i] = cd(rbar * (m->gmax * gs), rbar * w);
+            }
         }
-        const double cc = hc[i];
-        q[i] = cd(1.0, -2.0 * ha[i] * cc / w) / (hr[i] * cc * cc);
-        double gsum = 0.0;
-        for (int d = 0; d < D; ++d) gsum += prof_c[d][ix[d]];
-        const double gam = m->gmax * gsum;
-        Dp[i] = cd(gam, w) * q[i];
-        for (int e = 0; e < D; ++e) {
-            const int64_t nb = (ix[e] + 1 < g.n[e]) ? i + stride[e] : i - (int64_t)(g.n[e] - 1) * stride[e];
-            const double rbar = grid->collocated ? hr[i] : 0.5 * (hr[i] + hr[nb]);
-            rb[(size_t)e * N + i] = rbar;
-            double gs = 0.0;
-            for (int d = 0; d < D; ++d) gs += (d == e) ? prof_s[d][ix[d]] : prof_c[d][ix[d]];
-            Du[(size_t)e * N + i] = cd(rbar * (m->gmax * gs), rbar * w);
-        }
-    }
+    });
     // shifts (Algorithm 1 preprocessing) and scales (eq. C)
     if (grid->shift_rule == 1) {
         std::vector<double> v(Du.size());
@@ -1004,9 +1063,18 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
         m->a1 = cd(c1.x, c1.y);
         m->a2 = cd(c2.x, c2.y);
     }
-    double r1 = 0.0, r2 = 0.0;
-    for (const cd& v : Du) r1 = std::max(r1, std::abs(v - m->a1));
-    for (const cd& v : Dp) r2 = std::max(r2, std::abs(v - m->a2));
+    // max |D - a| (a maximum: exact whatever the chunking)
+    auto max_dist = [&](const std::vector<cd>& v, cd a) {
+        const int nc = plan_threads((int64_t)v.size());
+        std::vector<double> cm(nc, 0.0);
+        parallel_chunks((int64_t)v.size(), nc, [&](int c, int64_t lo, int64_t hi) {
+            double r = 0.0;
+            for (int64_t i = lo; i < hi; ++i) r = std::max(r, std::abs(v[i] - a));
+            cm[c] = r;
+        });
+        return *std::max_element(cm.begin(), cm.end());
+    };
+    const double r1 = max_dist(Du, m->a1), r2 = max_dist(Dp, m->a2);
     m->lam1 = std::max(r1, 1e-3 * std::abs(m->a1)) / m->beta;
     m->lam2 = std::max(r2, 1e-3 * std::abs(m->a2)) / m->beta;
 
@@ -1040,28 +1108,24 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
     m->rho64 = reinterpret_cast<double*>(base + o_r);
     m->alpha64 = reinterpret_cast<double*>(base + o_a);
 
-    std::vector<char> host(off, 0);
-    auto hput = [&](size_t o, const void* src, size_t bytes) { std::memcpy(host.data() + o, src, bytes); };
-    hput(o_rb64, rb.data(), sizeof(double) * D * N);
-    {
-        std::vector<cx<double>> q64(N);
-        std::vector<cx<float>> q32(N);
-        std::vector<float> rb32((size_t)D * N);
-        for (int64_t i = 0; i < N; ++i) {
-            q64[i] = {q[i].real(), q[i].imag()};
+    // Upload: the FP64 planes straight from the planner's arrays
+    // (std::complex<double> has the two-double layout of cx<double>), the FP32
+    // planes converted on host threads, the small per-axis tables staged in one
+    // buffer; one synchronisation at the end.
+    std::vector<float> rb32((size_t)D * N);
+    std::vector<cx<float>> q32(N);
+    parallel_chunks(N, plan_threads(N), [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
             q32[i] = {(float)q[i].real(), (float)q[i].imag()};
+            for (int e = 0; e < D; ++e) rb32[(size_t)e * N + i] = (float)rb[(size_t)e * N + i];
         }
-        for (size_t i = 0; i < rb.size(); ++i) rb32[i] = (float)rb[i];
-        hput(o_q64, q64.data(), sizeof(cx<double>) * N);
-        hput(o_q32, q32.data(), sizeof(cx<float>) * N);
-        hput(o_rb32, rb32.data(), sizeof(float) * D * N);
-    }
-    hput(o_c, hc.data(), sizeof(double) * N);
-    hput(o_r, hr.data(), sizeof(double) * N);
-    hput(o_a, ha.data(), sizeof(double) * N);
+    });
+    const size_t tab0 = o_tab64[0][0];   // the tables follow the planes
+    std::vector<char> tabs(off - tab0, 0);
+    auto tput = [&](size_t o, const void* src, size_t bytes) { std::memcpy(tabs.data() + (o - tab0), src, bytes); };
     for (int d = 0; d < 3; ++d) {
         const int n = g.n[d];
-        std::vector<double> kv(n), tr(n), ti(n);
+        std::vector<double> kv(n);
         std::vector<cx<double>> sh(n), tw(n);
         std::vector<float> kv32(n), gc32(n), gs32(n);
         std::vector<cx<float>> sh32(n), tw32(n);
@@ -1082,16 +1146,16 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
             gc32[j] = (float)prof_c[d][j];
             gs32[j] = (float)prof_s[d][j];
         }
-        hput(o_tab64[d][0], prof_c[d].data(), sizeof(double) * n);
-        hput(o_tab64[d][1], prof_s[d].data(), sizeof(double) * n);
-        hput(o_tab64[d][2], kv.data(), sizeof(double) * n);
-        hput(o_tab64[d][3], sh.data(), sizeof(cx<double>) * n);
-        hput(o_tab64[d][4], tw.data(), sizeof(cx<double>) * n);
-        hput(o_tab32[d][0], gc32.data(), sizeof(float) * n);
-        hput(o_tab32[d][1], gs32.data(), sizeof(float) * n);
-        hput(o_tab32[d][2], kv32.data(), sizeof(float) * n);
-        hput(o_tab32[d][3], sh32.data(), sizeof(cx<float>) * n);
-        hput(o_tab32[d][4], tw32.data(), sizeof(cx<float>) * n);
+        tput(o_tab64[d][0], prof_c[d].data(), sizeof(double) * n);
+        tput(o_tab64[d][1], prof_s[d].data(), sizeof(double) * n);
+        tput(o_tab64[d][2], kv.data(), sizeof(double) * n);
+        tput(o_tab64[d][3], sh.data(), sizeof(cx<double>) * n);
+        tput(o_tab64[d][4], tw.data(), sizeof(cx<double>) * n);
+        tput(o_tab32[d][0], gc32.data(), sizeof(float) * n);
+        tput(o_tab32[d][1], gs32.data(), sizeof(float) * n);
+        tput(o_tab32[d][2], kv32.data(), sizeof(float) * n);
+        tput(o_tab32[d][3], sh32.data(), sizeof(cx<float>) * n);
+        tput(o_tab32[d][4], tw32.data(), sizeof(cx<float>) * n);
         m->gc64[d] = reinterpret_cast<double*>(base + o_tab64[d][0]);
         m->gs64[d] = reinterpret_cast<double*>(base + o_tab64[d][1]);
         m->kv64[d] = reinterpret_cast<double*>(base + o_tab64[d][2]);
@@ -1103,8 +1167,20 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
         m->sh32[d] = reinterpret_cast<cx<float>*>(base + o_tab32[d][3]);
         m->tw32[d] = reinterpret_cast<cx<float>*>(base + o_tab32[d][4]);
     }
-    if (hipMemcpyAsync(m->dev, host.data(), off, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
+    static_assert(sizeof(cd) == sizeof(cx<double>), "complex layouts differ");
+    hipError_t ce = hipSuccess;
+    auto h2d = [&](size_t o, const void* src, size_t bytes) {
+        if (ce == hipSuccess) ce = hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    h2d(o_rb64, rb.data(), sizeof(double) * D * N);
+    h2d(o_q64, q.data(), sizeof(cx<double>) * N);
+    h2d(o_rb32, rb32.data(), sizeof(float) * D * N);
+    h2d(o_q32, q32.data(), sizeof(cx<float>) * N);
+    h2d(o_c, hc.data(), sizeof(double) * N);
+    h2d(o_r, hr.data(), sizeof(double) * N);
+    h2d(o_a, ha.data(), sizeof(double) * N);
+    h2d(tab0, tabs.data(), tabs.size());
+    if (ce != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
         (void)hipFree(m->dev);
         delete m;
         return CBS_E_DEVICE;

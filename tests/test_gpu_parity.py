@@ -54,6 +54,35 @@ def test_planner_scalars_match_oracle(orc, cbs, shape, rule):
         assert abs(so[k] - sg[k]) <= 1e-12 * so[k], (k, so[k], sg[k])
 
 
+def _structured(name):
+    """Media whose diagonal values repeat or line up: the 2-D disc workload
+    (water background: millions of equal values at full size), a homogeneous
+    3-D medium (every cell outside the absorbing layer on one point), and the
+    3-D random medium (continuous values); each large enough for the host
+    planner to split its scans over threads."""
+    if name == "disc2d":
+        pr = W.disc2d(256)
+        return pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, 16
+    if name == "water3d":
+        shape = (48, 48, 48)
+        return shape, DX, OMEGA, np.full(shape, 1500.0), np.full(shape, 1000.0), np.zeros(shape), 6
+    pr = W.random3d(48)
+    return pr.shape, pr.dx, pr.omega, pr.c, pr.rho, pr.alpha, 6
+
+
+@pytest.mark.parametrize("name", ["disc2d", "water3d", "random3d"])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_planner_scalars_structured_media(orc, cbs, name, rule):
+    shape, dx, omega, c, rho, alpha, pml = _structured(name)
+    om = orc.OracleMedium(shape, dx, omega, c, rho, alpha, pml=pml, shift_rule=rule)
+    gm = cbs.Medium(shape, dx, omega, c, rho, alpha, pml=pml, shift_rule=rule)
+    so, sg = om.scalars(), gm.scalars()
+    for k in ("a1", "a2"):
+        assert abs(so[k] - sg[k]) <= 1e-12 * abs(so[k]), (k, so[k], sg[k])
+    for k in ("lam1", "lam2"):
+        assert abs(so[k] - sg[k]) <= 1e-12 * so[k], (k, so[k], sg[k])
+
+
 @pytest.mark.parametrize("shape", SHAPES + [(128, 128), (64, 64, 64)])
 @pytest.mark.parametrize("adjoint", [False, True])
 @pytest.mark.parametrize("iters", [1, 7, 60])
