@@ -150,6 +150,16 @@ cbs_status cbs_destroy_medium(cbs_medium m);
  * lam1, lam2, beta, nu. */
 cbs_status cbs_medium_scalars(cbs_medium m, double out[8]);
 
+/* The same scalars computed on the host alone, without a device or a medium
+ * handle (Algorithm 1 preprocessing; shifts per grid->shift_rule: centre of
+ * the minimum enclosing circle of each diagonal's values, or their
+ * component-wise median; scales per eq. C).  c, rho, alpha: host arrays of
+ * prod(n) float64, read only during the call.  out[0..7] as
+ * cbs_medium_scalars; a medium created from the same arguments reports the
+ * same values.  CBS_E_INVALID / CBS_E_UNSUPPORTED as cbs_create_medium. */
+cbs_status cbs_plan_scalars(const cbs_grid *grid, const double *c, const double *rho,
+                            const double *alpha, double out[8]);
+
 /* Override the split scalars: in[0..5] = Re a1, Im a1, Re a2, Im a2, lam1,
  * lam2 (lam > 0).  Changes the iteration, not its fixed point. */
 cbs_status cbs_set_scalars(cbs_medium m, const double in[6]);

@@ -32,7 +32,7 @@ CBS_STOP_RESIDUAL = 1
 
 # every entry point declared in include/cbs.h
 EXPORTS = [
-    "cbs_create_medium", "cbs_destroy_medium", "cbs_medium_scalars", "cbs_set_scalars",
+    "cbs_create_medium", "cbs_destroy_medium", "cbs_medium_scalars", "cbs_plan_scalars", "cbs_set_scalars",
     "cbs_workspace_bytes", "cbs_solve", "cbs_solve_adjoint", "cbs_residual", "cbs_gradient",
     "cbs_pass_config", "cbs_pass_timing", "cbs_pass_timing_slots", "cbs_pass_timing_read",
     "cbs_batch_workspace_bytes", "cbs_batch_create", "cbs_batch_destroy", "cbs_batch_submit",
@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
     L.cbs_create_medium.argtypes = [C.POINTER(Grid), vp, vp, vp, i32, vp, C.POINTER(vp)]
     L.cbs_destroy_medium.argtypes = [vp]
     L.cbs_medium_scalars.argtypes = [vp, dp]
+    L.cbs_plan_scalars.argtypes = [C.POINTER(Grid), vp, vp, vp, dp]
     L.cbs_set_scalars.argtypes = [vp, dp]
     L.cbs_workspace_bytes.argtypes = [vp, i32, i32, C.POINTER(C.c_size_t)]
     solve_args = [vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, C.c_size_t, C.POINTER(SolveInfo), vp]

@@ -950,6 +950,143 @@ cbs_status validate_grid(const cbs_grid* g) {
     return CBS_OK;
 }
 
+// Host part of the medium planner (Algorithm 1 preprocessing): layer
+// profiles, q and the staggered densities, the diagonal values, the shifts
+// a1, a2 (minimum enclosing circle or median) and the scales lam1, lam2
+// (eq. C).  Inputs are validated host arrays of g.ncell values.
+struct HostPlan {
+    std::vector<double> prof_c[3], prof_s[3];   // layer r^2 at centres / staggered points
+    std::vector<cd> q;                          // (1 - 2i alpha c / omega) / (rho c^2)
+    std::vector<double> rb;                     // staggered densities, ndim planes
+    cd a1, a2;
+    double lam1 = 0, lam2 = 0, gmax = 0, beta = 0, nu = 0;
+};
+
+void plan_medium(const cbs_grid& grid, const Geom& g, const double* hc, const double* hr, const double* ha,
+                 HostPlan* hp) {
+    hp->gmax = grid.pml_gamma_max > 0 ? grid.pml_gamma_max : grid.omega;
+    hp->beta = grid.beta == 0 ? 0.95 : grid.beta;
+    hp->nu = grid.nu == 0 ? 0.9 : grid.nu;
+    const double w = grid.omega;
+    const int L = grid.pml_cells;
+    const int D = g.ndim;
+    const int64_t N = g.ncell;
+
+    // per-axis layer profiles r^2 at centres and staggered points
+    std::vector<double>* prof_c = hp->prof_c;
+    std::vector<double>* prof_s = hp->prof_s;
+    for (int d = 0; d < 3; ++d) {
+        prof_c[d].assign(g.n[d], 0.0);
+        prof_s[d].assign(g.n[d], 0.0);
+        if (d >= D) continue;
+        const double half = grid.collocated ? 0.0 : 0.5;   // velocity rows' position
+        for (int i = 0; i < g.n[d]; ++i) {
+            const double rc = layer_frac(i, g.n[d], L), rs = layer_frac(i + half, g.n[d], L);
+            prof_c[d][i] = rc * rc;
+            prof_s[d][i] = rs * rs;
+        }
+    }
+    // q, staggered density, diagonal values for the shifts
+    std::vector<cd>& q = hp->q;
+    std::vector<double>& rb = hp->rb;
+    q.assign(N, cd());
+    rb.assign((size_t)D * N, 0.0);
+    std::vector<cd> Du((size_t)D * N), Dp(N);
+    int64_t stride[3] = {1, 1, 1};
+    for (int d = D - 2; d >= 0; --d) stride[d] = stride[d + 1] * g.n[d + 1];
+    const int nt = plan_threads(N);
+    parallel_chunks(N, nt, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            int ix[3] = {0, 0, 0};
+            int64_t r = i;
+            for (int d = D - 1; d >= 0; --d) {
+                ix[d] = (int)(r % g.n[d]);
+                r /= g.n[d];
+            }
+            const double cc = hc[i];
+            q[i] = cd(1.0, -2.0 * ha[i] * cc / w) / (hr[i] * cc * cc);
+            double gsum = 0.0;
+            for (int d = 0; d < D; ++d) gsum += prof_c[d][ix[d]];
+            const double gam = hp->gmax * gsum;
+            Dp[i] = cd(gam, w) * q[i];
+            for (int e = 0; e < D; ++e) {
+                const int64_t nb = (ix[e] + 1 < g.n[e]) ? i + stride[e] : i - (int64_t)(g.n[e] - 1) * stride[e];
+                const double rbar = grid.collocated ? hr[i] : 0.5 * (hr[i] + hr[nb]);
+                rb[(size_t)e * N + i] = rbar;
+                double gs = 0.0;
+                for (int d = 0; d < D; ++d) gs += (d == e) ? prof_s[d][ix[d]] : prof_c[d][ix[d]];
+                Du[(size_t)e * N + i] = cd(rbar * (hp->gmax * gs), rbar * w);
+            }
+        }
+    });
+    // shifts (Algorithm 1 preprocessing) and scales (eq. C)
+    if (grid.shift_rule == 1) {
+        std::vector<double> v(Du.size());
+        for (size_t i = 0; i < Du.size(); ++i) v[i] = Du[i].real();
+        const double r1 = median(v);
+        for (size_t i = 0; i < Du.size(); ++i) v[i] = Du[i].imag();
+        hp->a1 = cd(r1, median(v));
+        v.resize(Dp.size());
+        for (size_t i = 0; i < Dp.size(); ++i) v[i] = Dp[i].real();
+        const double r2 = median(v);
+        for (size_t i = 0; i < Dp.size(); ++i) v[i] = Dp[i].imag();
+        hp->a2 = cd(r2, median(v));
+    } else {
+        Circle c1 = min_circle(Du), c2 = min_circle(Dp);
+        hp->a1 = cd(c1.x, c1.y);
+        hp->a2 = cd(c2.x, c2.y);
+    }
+    // max |D - a| (a maximum: exact whatever the chunking)
+    auto max_dist = [&](const std::vector<cd>& v, cd a) {
+        const int nc = plan_threads((int64_t)v.size());
+        std::vector<double> cm(nc, 0.0);
+        parallel_chunks((int64_t)v.size(), nc, [&](int c, int64_t lo, int64_t hi) {
+            double r = 0.0;
+            for (int64_t i = lo; i < hi; ++i) r = std::max(r, std::abs(v[i] - a));
+            cm[c] = r;
+        });
+        return *std::max_element(cm.begin(), cm.end());
+    };
+    const double r1 = max_dist(Du, hp->a1), r2 = max_dist(Dp, hp->a2);
+    hp->lam1 = std::max(r1, 1e-3 * std::abs(hp->a1)) / hp->beta;
+    hp->lam2 = std::max(r2, 1e-3 * std::abs(hp->a2)) / hp->beta;
+}
+
+// Host copies of c, rho, alpha (from host or device memory), checked:
+// c > 0, rho > 0, alpha >= 0, all finite.
+cbs_status host_medium(const Geom& g, const double* c, const double* rho, const double* alpha, int32_t ptr_kind,
+                       hipStream_t st, std::vector<double>* hc, std::vector<double>* hr, std::vector<double>* ha) {
+    const int64_t N = g.ncell;
+    hc->resize(N);
+    hr->resize(N);
+    ha->resize(N);
+    if (ptr_kind == CBS_PTR_DEVICE) {
+        HIPOK(hipMemcpyAsync(hc->data(), c, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipMemcpyAsync(hr->data(), rho, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipMemcpyAsync(ha->data(), alpha, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(hc->data(), c, N * sizeof(double));
+        std::memcpy(hr->data(), rho, N * sizeof(double));
+        std::memcpy(ha->data(), alpha, N * sizeof(double));
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        const double cv = (*hc)[i], rv = (*hr)[i], av = (*ha)[i];
+        if (!(cv > 0) || !(rv > 0) || !(av >= 0) || !std::isfinite(cv) || !std::isfinite(rv) || !std::isfinite(av))
+            return CBS_E_INVALID;
+    }
+    return CBS_OK;
+}
+
+Geom geom_of(const cbs_grid& grid) {
+    Geom g{};
+    g.ndim = grid.ndim;
+    g.ncell = 1;
+    for (int d = 0; d < 3; ++d) g.n[d] = d < grid.ndim ? (int)grid.n[d] : 1;
+    for (int d = 0; d < grid.ndim; ++d) g.ncell *= g.n[d];
+    return g;
+}
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -967,116 +1104,31 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
     if (!c || !rho || !alpha) return CBS_E_INVALID;
     if (ptr_kind != CBS_PTR_HOST && ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
     hipStream_t st = (hipStream_t)hip_stream;
-    const int D = grid->ndim;
-    Geom g{};
-    g.ndim = D;
-    g.ncell = 1;
-    for (int d = 0; d < 3; ++d) g.n[d] = d < D ? (int)grid->n[d] : 1;
-    for (int d = 0; d < D; ++d) g.ncell *= g.n[d];
+    const Geom g = geom_of(*grid);
+    const int D = g.ndim;
     const int64_t N = g.ncell;
-
-    // host copies of the medium
-    std::vector<double> hc(N), hr(N), ha(N);
-    if (ptr_kind == CBS_PTR_DEVICE) {
-        HIPOK(hipMemcpyAsync(hc.data(), c, N * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPOK(hipMemcpyAsync(hr.data(), rho, N * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPOK(hipMemcpyAsync(ha.data(), alpha, N * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPOK(hipStreamSynchronize(st));
-    } else {
-        std::memcpy(hc.data(), c, N * sizeof(double));
-        std::memcpy(hr.data(), rho, N * sizeof(double));
-        std::memcpy(ha.data(), alpha, N * sizeof(double));
-    }
-    for (int64_t i = 0; i < N; ++i)
-        if (!(hc[i] > 0) || !(hr[i] > 0) || !(ha[i] >= 0) || !std::isfinite(hc[i]) || !std::isfinite(hr[i]) ||
-            !std::isfinite(ha[i]))
-            return CBS_E_INVALID;
+    std::vector<double> hc, hr, ha;
+    cbs_status hs = host_medium(g, c, rho, alpha, ptr_kind, st, &hc, &hr, &ha);
+    if (hs != CBS_OK) return hs;
 
     cbs_medium_s* m = new (std::nothrow) cbs_medium_s();
     if (!m) return CBS_E_NOMEM;
     m->g = g;
     m->grid = *grid;
-    m->gmax = grid->pml_gamma_max > 0 ? grid->pml_gamma_max : grid->omega;
-    m->beta = grid->beta == 0 ? 0.95 : grid->beta;
-    m->nu = grid->nu == 0 ? 0.9 : grid->nu;
-    const double w = grid->omega, dx = grid->dx;
-    const int L = grid->pml_cells;
-
-    // per-axis layer profiles r^2 at centres and staggered points
-    std::vector<double> prof_c[3], prof_s[3];
-    for (int d = 0; d < 3; ++d) {
-        prof_c[d].assign(g.n[d], 0.0);
-        prof_s[d].assign(g.n[d], 0.0);
-        if (d >= D) continue;
-        const double half = grid->collocated ? 0.0 : 0.5;   // velocity rows' position
-        for (int i = 0; i < g.n[d]; ++i) {
-            const double rc = layer_frac(i, g.n[d], L), rs = layer_frac(i + half, g.n[d], L);
-            prof_c[d][i] = rc * rc;
-            prof_s[d][i] = rs * rs;
-        }
-    }
-    // q, staggered density, diagonal values for the shifts
-    std::vector<cd> q(N);
-    std::vector<double> rb((size_t)D * N);
-    std::vector<cd> Du((size_t)D * N), Dp(N);
-    int64_t stride[3] = {1, 1, 1};
-    for (int d = D - 2; d >= 0; --d) stride[d] = stride[d + 1] * g.n[d + 1];
-    const int nt = plan_threads(N);
-    parallel_chunks(N, nt, [&](int, int64_t lo, int64_t hi) {
-        for (int64_t i = lo; i < hi; ++i) {
-            int ix[3] = {0, 0, 0};
-            int64_t r = i;
-            for (int d = D - 1; d >= 0; --d) {
-                ix[d] = (int)(r % g.n[d]);
-                r /= g.n[d];
-            }
-            const double cc = hc[i];
-            q[i] = cd(1.0, -2.0 * ha[i] * cc / w) / (hr[i] * cc * cc);
-            double gsum = 0.0;
-            for (int d = 0; d < D; ++d) gsum += prof_c[d][ix[d]];
-            const double gam = m->gmax * gsum;
-            Dp[i] = cd(gam, w) * q[i];
-            for (int e = 0; e < D; ++e) {
-                const int64_t nb = (ix[e] + 1 < g.n[e]) ? i + stride[e] : i - (int64_t)(g.n[e] - 1) * stride[e];
-                const double rbar = grid->collocated ? hr[i] : 0.5 * (hr[i] + hr[nb]);
-                rb[(size_t)e * N + i] = rbar;
-                double gs = 0.0;
-                for (int d = 0; d < D; ++d) gs += (d == e) ? prof_s[d][ix[d]] : prof_c[d][ix[d]];
-                Du[(size_t)e * N + i] = cd(rbar * (m->gmax * gs), rbar * w);
-            }
-        }
-    });
-    // shifts (Algorithm 1 preprocessing) and scales (eq. C)
-    if (grid->shift_rule == 1) {
-        std::vector<double> v(Du.size());
-        for (size_t i = 0; i < Du.size(); ++i) v[i] = Du[i].real();
-        const double r1 = median(v);
-        for (size_t i = 0; i < Du.size(); ++i) v[i] = Du[i].imag();
-        m->a1 = cd(r1, median(v));
-        v.resize(Dp.size());
-        for (size_t i = 0; i < Dp.size(); ++i) v[i] = Dp[i].real();
-        const double r2 = median(v);
-        for (size_t i = 0; i < Dp.size(); ++i) v[i] = Dp[i].imag();
-        m->a2 = cd(r2, median(v));
-    } else {
-        Circle c1 = min_circle(Du), c2 = min_circle(Dp);
-        m->a1 = cd(c1.x, c1.y);
-        m->a2 = cd(c2.x, c2.y);
-    }
-    // max |D - a| (a maximum: exact whatever the chunking)
-    auto max_dist = [&](const std::vector<cd>& v, cd a) {
-        const int nc = plan_threads((int64_t)v.size());
-        std::vector<double> cm(nc, 0.0);
-        parallel_chunks((int64_t)v.size(), nc, [&](int c, int64_t lo, int64_t hi) {
-            double r = 0.0;
-            for (int64_t i = lo; i < hi; ++i) r = std::max(r, std::abs(v[i] - a));
-            cm[c] = r;
-        });
-        return *std::max_element(cm.begin(), cm.end());
-    };
-    const double r1 = max_dist(Du, m->a1), r2 = max_dist(Dp, m->a2);
-    m->lam1 = std::max(r1, 1e-3 * std::abs(m->a1)) / m->beta;
-    m->lam2 = std::max(r2, 1e-3 * std::abs(m->a2)) / m->beta;
+    const double dx = grid->dx;
+    HostPlan hp;
+    plan_medium(*grid, g, hc.data(), hr.data(), ha.data(), &hp);
+    m->gmax = hp.gmax;
+    m->a1 = hp.a1;
+    m->a2 = hp.a2;
+    m->lam1 = hp.lam1;
+    m->lam2 = hp.lam2;
+    m->beta = hp.beta;
+    m->nu = hp.nu;
+    const std::vector<double>* prof_c = hp.prof_c;
+    const std::vector<double>* prof_s = hp.prof_s;
+    const std::vector<cd>& q = hp.q;
+    const std::vector<double>& rb = hp.rb;
 
     // device block: FP64 medium, FP32 medium, physical fields, axis tables
     size_t off = 0;
@@ -1209,6 +1261,23 @@ cbs_status cbs_medium_scalars(cbs_medium m, double out[8]) {
     out[5] = m->lam2;
     out[6] = m->beta;
     out[7] = m->nu;
+    return CBS_OK;
+}
+
+cbs_status cbs_plan_scalars(const cbs_grid* grid, const double* c, const double* rho, const double* alpha,
+                            double out[8]) {
+    if (!out) return CBS_E_INVALID;
+    cbs_status vs = validate_grid(grid);
+    if (vs != CBS_OK) return vs;
+    if (!c || !rho || !alpha) return CBS_E_INVALID;
+    const Geom g = geom_of(*grid);
+    std::vector<double> hc, hr, ha;
+    cbs_status hs = host_medium(g, c, rho, alpha, CBS_PTR_HOST, nullptr, &hc, &hr, &ha);
+    if (hs != CBS_OK) return hs;
+    HostPlan hp;
+    plan_medium(*grid, g, hc.data(), hr.data(), ha.data(), &hp);
+    const double v[8] = {hp.a1.real(), hp.a1.imag(), hp.a2.real(), hp.a2.imag(), hp.lam1, hp.lam2, hp.beta, hp.nu};
+    std::memcpy(out, v, sizeof v);
     return CBS_OK;
 }
 

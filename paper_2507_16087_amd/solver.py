@@ -64,6 +64,33 @@ def _dev_c128(a, count):
     return a
 
 
+def _grid(shape, dx, omega, pml, gamma_max, beta, nu, shift_rule, collocated):
+    g = L.Grid()
+    g.ndim = len(shape)
+    for d in range(3):
+        g.n[d] = shape[d] if d < len(shape) else 1
+    g.dx, g.omega, g.pml_cells, g.pml_gamma_max = float(dx), float(omega), int(pml), float(gamma_max)
+    g.beta, g.nu, g.shift_rule = float(beta), float(nu), int(shift_rule)
+    g.collocated = int(bool(collocated))
+    return g
+
+
+def plan_scalars(shape: Sequence[int], dx: float, omega: float, c, rho, alpha, pml: int = 16,
+                 gamma_max: float = 0.0, beta: float = 0.95, nu: float = 0.9, shift_rule: int = 0,
+                 collocated: bool = False) -> dict:
+    """The split scalars (shifts a1, a2, scales lam1, lam2, beta, nu) a medium
+    of these arguments would use, computed on the host alone (no GPU)."""
+    shape = tuple(int(s) for s in shape)
+    g = _grid(shape, dx, omega, pml, gamma_max, beta, nu, shift_rule, collocated)
+    n = int(np.prod(shape))
+    arrs = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (c, rho, alpha)]
+    if any(a.size != n for a in arrs):
+        raise ValueError("medium arrays must have prod(shape) cells")
+    o = (C.c_double * 8)()
+    L.check(L.lib().cbs_plan_scalars(C.byref(g), *[_ptr(a) for a in arrs], o), "cbs_plan_scalars")
+    return dict(a1=complex(o[0], o[1]), a2=complex(o[2], o[3]), lam1=o[4], lam2=o[5], beta=o[6], nu=o[7])
+
+
 class Medium:
     """A medium (c, rho, alpha on the grid) planned for the solver."""
 
@@ -75,13 +102,7 @@ class Medium:
         self.ncell = int(np.prod(self.shape))
         self.F = self.ndim + 1
         self.dx, self.omega = float(dx), float(omega)
-        g = L.Grid()
-        g.ndim = self.ndim
-        for d in range(3):
-            g.n[d] = self.shape[d] if d < self.ndim else 1
-        g.dx, g.omega, g.pml_cells, g.pml_gamma_max = self.dx, self.omega, int(pml), float(gamma_max)
-        g.beta, g.nu, g.shift_rule = float(beta), float(nu), int(shift_rule)
-        g.collocated = int(bool(collocated))
+        g = _grid(self.shape, dx, omega, pml, gamma_max, beta, nu, shift_rule, collocated)
         self.grid = g
         if _is_tensor(c):
             arrs = [t.contiguous().to(_torch().float64) for t in (c, rho, alpha)]
