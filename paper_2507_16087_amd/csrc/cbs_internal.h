@@ -12,7 +12,7 @@ struct alignas(2 * sizeof(T)) cx {
 };
 
 // Partial-sum pairs one reduction block folds.
-constexpr int kReduceChunk = 4096;
+constexpr int kReduceChunk = 1024;
 
 // Per-solve control block in device memory.  Written by the reduction
 // kernels, read by every pass kernel (a finished slot's passes exit at once)

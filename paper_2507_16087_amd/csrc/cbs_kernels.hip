@@ -896,8 +896,9 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
 // ---------------------------------------------------------- reductions --
 // Two levels, one launch: grid = (blocks, slots); block b folds partial pairs
 // [b * kReduceChunk, (b + 1) * kReduceChunk) into chunks[b]; the block that
-// arrives last folds the chunk sums in index order (so the totals do not
-// depend on scheduling) and finalises the slot's control block
+// arrives last folds the chunk sums with all its threads (thread t takes
+// chunks t, t + 256, ... in order, then the block's fixed tree), so the
+// totals do not depend on scheduling, and finalises the slot's control block
 // (finalize_ctl).
 template <typename T, bool CBSMODE>
 __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* slots, int nparts) {
@@ -924,13 +925,14 @@ __global__ void __launch_bounds__(256) k_reduce(const Slot<T>* slots, int nparts
     __syncthreads();
     if (!last) return;
     __threadfence();
-    if (threadIdx.x != 0) return;
     a = 0.0;
     b = 0.0;
-    for (int i = 0; i < (int)gridDim.x; ++i) {
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
         a += ((volatile double*)s.chunks)[2 * i];
         b += ((volatile double*)s.chunks)[2 * i + 1];
     }
+    block_sum2(a, b, red);
+    if (threadIdx.x != 0) return;
     c->arrive = 0;
     finalize_ctl<CBSMODE>(c, a, b);
 }
