@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <mutex>
 #include <cstdio>
@@ -182,13 +183,24 @@ Circle from3(double ax, double ay, double bx, double by, double cx_, double cy_)
 // Run body(lo, hi) over [0, n) in contiguous chunks, one per host thread (at
 // most 16), the first on the calling thread.  Chunks are returned in order by
 // the caller's own bookkeeping, so results do not depend on the thread count.
+// An exception thrown in any chunk (an allocation failing) is rethrown on
+// the calling thread after every chunk has finished.
 template <class F>
 void parallel_chunks(int64_t n, int nchunks, F&& body) {
+    std::vector<std::exception_ptr> err(nchunks);
+    auto run = [&](int c) {
+        try {
+            body(c, n * c / nchunks, n * (c + 1) / nchunks);
+        } catch (...) {
+            err[c] = std::current_exception();
+        }
+    };
     std::vector<std::thread> pool;
-    for (int c = 1; c < nchunks; ++c)
-        pool.emplace_back([&, c] { body(c, n * c / nchunks, n * (c + 1) / nchunks); });
-    body(0, 0, n / nchunks);
+    for (int c = 1; c < nchunks; ++c) pool.emplace_back(run, c);
+    run(0);
     for (std::thread& t : pool) t.join();
+    for (const std::exception_ptr& e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 int plan_threads(int64_t n) {
@@ -1091,14 +1103,18 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-}  // namespace
+// Frees a partly built medium (device block included) unless released.
+struct MediumOwner {
+    cbs_medium_s* m;
+    ~MediumOwner() {
+        if (!m) return;
+        if (m->dev) (void)hipFree(m->dev);
+        delete m;
+    }
+};
 
-extern "C" {
-
-cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double* rho, const double* alpha,
-                             int32_t ptr_kind, void* hip_stream, cbs_medium* out) {
-    if (!out) return CBS_E_INVALID;
-    *out = nullptr;
+cbs_status create_medium(const cbs_grid* grid, const double* c, const double* rho, const double* alpha,
+                                int32_t ptr_kind, void* hip_stream, cbs_medium* out) {
     cbs_status vs = validate_grid(grid);
     if (vs != CBS_OK) return vs;
     if (!c || !rho || !alpha) return CBS_E_INVALID;
@@ -1113,6 +1129,7 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
 
     cbs_medium_s* m = new (std::nothrow) cbs_medium_s();
     if (!m) return CBS_E_NOMEM;
+    MediumOwner own{m};
     m->g = g;
     m->grid = *grid;
     const double dx = grid->dx;
@@ -1148,7 +1165,7 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
         for (int t = 3; t < 5; ++t) o_tab32[d][t] = take(sizeof(cx<float>) * g.n[d]);
     }
     if (hipMalloc(&m->dev, off) != hipSuccess) {
-        delete m;
+        m->dev = nullptr;
         return CBS_E_NOMEM;
     }
     char* base = static_cast<char*>(m->dev);
@@ -1232,15 +1249,36 @@ cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double
     h2d(o_r, hr.data(), sizeof(double) * N);
     h2d(o_a, ha.data(), sizeof(double) * N);
     h2d(tab0, tabs.data(), tabs.size());
-    if (ce != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
-        (void)hipFree(m->dev);
-        delete m;
-        return CBS_E_DEVICE;
-    }
+    if (ce != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return CBS_E_DEVICE;
     m->ps64 = make_passes(g, true);
     m->ps32 = make_passes(g, false);
+    own.m = nullptr;
     *out = m;
     return CBS_OK;
+}
+
+// No C++ exception crosses the C ABI: a failed host allocation is
+// CBS_E_NOMEM, anything else CBS_E_INVALID.
+template <class F>
+cbs_status guarded(F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return CBS_E_NOMEM;
+    } catch (...) {
+        return CBS_E_INVALID;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+cbs_status cbs_create_medium(const cbs_grid* grid, const double* c, const double* rho, const double* alpha,
+                             int32_t ptr_kind, void* hip_stream, cbs_medium* out) {
+    if (!out) return CBS_E_INVALID;
+    *out = nullptr;
+    return guarded([&] { return create_medium(grid, c, rho, alpha, ptr_kind, hip_stream, out); });
 }
 
 cbs_status cbs_destroy_medium(cbs_medium m) {
@@ -1270,15 +1308,18 @@ cbs_status cbs_plan_scalars(const cbs_grid* grid, const double* c, const double*
     cbs_status vs = validate_grid(grid);
     if (vs != CBS_OK) return vs;
     if (!c || !rho || !alpha) return CBS_E_INVALID;
-    const Geom g = geom_of(*grid);
-    std::vector<double> hc, hr, ha;
-    cbs_status hs = host_medium(g, c, rho, alpha, CBS_PTR_HOST, nullptr, &hc, &hr, &ha);
-    if (hs != CBS_OK) return hs;
-    HostPlan hp;
-    plan_medium(*grid, g, hc.data(), hr.data(), ha.data(), &hp);
-    const double v[8] = {hp.a1.real(), hp.a1.imag(), hp.a2.real(), hp.a2.imag(), hp.lam1, hp.lam2, hp.beta, hp.nu};
-    std::memcpy(out, v, sizeof v);
-    return CBS_OK;
+    return guarded([&] {
+        const Geom g = geom_of(*grid);
+        std::vector<double> hc, hr, ha;
+        cbs_status hs = host_medium(g, c, rho, alpha, CBS_PTR_HOST, nullptr, &hc, &hr, &ha);
+        if (hs != CBS_OK) return hs;
+        HostPlan hp;
+        plan_medium(*grid, g, hc.data(), hr.data(), ha.data(), &hp);
+        const double v[8] = {hp.a1.real(), hp.a1.imag(), hp.a2.real(), hp.a2.imag(),
+                             hp.lam1,      hp.lam2,      hp.beta,      hp.nu};
+        std::memcpy(out, v, sizeof v);
+        return CBS_OK;
+    });
 }
 
 cbs_status cbs_set_scalars(cbs_medium m, const double in[6]) {
