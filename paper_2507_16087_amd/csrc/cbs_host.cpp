@@ -1557,13 +1557,13 @@ extern "C" {
 
 cbs_status cbs_solve(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts, void* p_out,
                      void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info, void* hip_stream) {
-    return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 0);
+    return guarded([&] { return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 0); });
 }
 
 cbs_status cbs_solve_adjoint(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts,
                              void* p_out, void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info,
                              void* hip_stream) {
-    return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 1);
+    return guarded([&] { return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 1); });
 }
 
 cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,
@@ -1578,7 +1578,7 @@ cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const vo
     const Geom& g = m->g;
     const int64_t N = g.ncell;
     const int D = g.ndim;
-    cbs_status ts = ensure_tuned(m, CBS_FP64, workspace, st);
+    cbs_status ts = guarded([&] { return ensure_tuned(m, CBS_FP64, workspace, st); });
     if (ts != CBS_OK) return ts;
     Slot<double>* dslot = at<Slot<double>>(workspace, L.off_slot64);
     Ctl* ctl = at<Ctl>(workspace, L.off_ctl64);
@@ -1902,6 +1902,22 @@ cbs_status batch_cbs_phase(cbs_batch_s* b, int iterations, Slot<T>* dc, Slot<T>*
     return CBS_OK;
 }
 
+// One step of every active slot: residual phase (refined precision), then
+// `iterations` CBS iterations; done_mask marks finished slots.
+cbs_status batch_step(cbs_batch_s* b, int32_t iterations, uint8_t* done_mask) {
+    cbs_status cs = CBS_OK;
+    if (b->prec == CBS_FP32_REFINED) {
+        if ((cs = batch_residual_phase(b)) != CBS_OK) return cs;
+        cs = batch_cbs_phase<float>(b, iterations, b->dc32, b->hc32, b->ps32);
+    } else {
+        cs = batch_cbs_phase<double>(b, iterations, b->dc64, b->hc64, b->ps64);
+    }
+    if (cs != CBS_OK) return cs;
+    if (done_mask)
+        for (int i = 0; i < b->maxs; ++i) done_mask[i] = b->s[i].phase == PH_DONE ? 1 : 0;
+    return CBS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1977,7 +1993,7 @@ cbs_status cbs_batch_submit(cbs_batch b, cbs_medium m, const void* s_p, const vo
     if (i == b->maxs) return CBS_E_NOMEM;
     char* ws = b->region(i);
     if (!b->have_plans) {
-        cbs_status ts = ensure_tuned(m, b->prec, ws, b->st);
+        cbs_status ts = guarded([&] { return ensure_tuned(m, b->prec, ws, b->st); });
         if (ts != CBS_OK) return ts;
         b->ps64 = m->ps64;
         b->ps32 = m->ps32;
@@ -2022,17 +2038,7 @@ cbs_status cbs_batch_submit(cbs_batch b, cbs_medium m, const void* s_p, const vo
 
 cbs_status cbs_batch_step(cbs_batch b, int32_t iterations, uint8_t* done_mask) {
     if (!b || iterations < 1) return CBS_E_INVALID;
-    cbs_status cs = CBS_OK;
-    if (b->prec == CBS_FP32_REFINED) {
-        if ((cs = batch_residual_phase(b)) != CBS_OK) return cs;
-        cs = batch_cbs_phase<float>(b, iterations, b->dc32, b->hc32, b->ps32);
-    } else {
-        cs = batch_cbs_phase<double>(b, iterations, b->dc64, b->hc64, b->ps64);
-    }
-    if (cs != CBS_OK) return cs;
-    if (done_mask)
-        for (int i = 0; i < b->maxs; ++i) done_mask[i] = b->s[i].phase == PH_DONE ? 1 : 0;
-    return CBS_OK;
+    return guarded([&] { return batch_step(b, iterations, done_mask); });
 }
 
 cbs_status cbs_batch_retire(cbs_batch b, int32_t slot, void* p_out, void* u_out, int32_t ptr_kind,
