@@ -239,7 +239,9 @@ cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
  * CBS_COLUMN_BLOCKS (1, 2, 4, 8) pin a choice, tuned or not; CBS_TUNE_FILE
  * names a text file that keeps tuned sets across processes (one line per
  * device architecture, shape, precision and pins; read before tuning, a
- * newly tuned set appended; lines that do not fit their shape are ignored).
+ * newly tuned set appended; lines that do not fit their shape are ignored,
+ * the others are used without timing them again, so a line edited by hand
+ * that a launch refuses makes solves fail with CBS_E_DEVICE).
  * Configurations
  * needing more than 160 KiB of LDS are never launched.  CBS_E_INVALID for a
  * null argument or a prec other than CBS_FP64 and CBS_FP32_REFINED. */
