@@ -90,6 +90,26 @@ template <typename T>
 __device__ __forceinline__ T ldg(const GLOBAL T* p) {
     return *p;
 }
+// Non-temporal loads and stores for the streams the last-axis passes touch
+// once per iteration (x, y and the medium read, x written): marked so, they
+// leave more of the caches to the FFT work array w, which the next passes
+// read again.
+template <typename T>
+__device__ __forceinline__ cx<T> ld_nt(const GLOBAL cx<T>* p) {
+    using V = T __attribute__((ext_vector_type(2)));
+    const V v = __builtin_nontemporal_load((const GLOBAL V*)p);
+    return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(GLOBAL cx<T>* p, cx<T> a) {
+    using V = T __attribute__((ext_vector_type(2)));
+    V v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, (GLOBAL V*)p);
+}
+__device__ __forceinline__ float ld_nt(const GLOBAL float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ld_nt(const GLOBAL double* p) { return __builtin_nontemporal_load(p); }
 
 // ------------------------------------------------ compile-time twiddles --
 constexpr double kPi = 3.14159265358979323846264338327950288;
@@ -560,8 +580,8 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
     // medium value at element n: rhobar (real part) on velocity rows, q on
     // the pressure row
     auto medium = [&](int n) -> cx<T> {
-        if (urow) return {rb[n], T(0)};
-        return qv[n];
+        if (urow) return {ld_nt(rb + n), T(0)};
+        return ld_nt(qv + n);
     };
     // diagonal D (conjugated for the adjoint) at element n from its medium value
     auto diag_m = [&](int n, cx<T> m) -> cx<T> {
@@ -582,11 +602,11 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int n = in_index<P, -1>(lane, b, r);
-                const cx<T> xv = x[pl + n];
+                const cx<T> xv = ld_nt(x + pl + n);
                 if constexpr (MODE == CBS) {
                     const cx<T> dd = diag(n);
                     const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
-                    v[b * R0 + r] = cmul(bb, xv) + y[pl + n];
+                    v[b * R0 + r] = cmul(bb, xv) + ld_nt(y + pl + n);
                 } else {
                     v[b * R0 + r] = xv;
                 }
@@ -606,9 +626,9 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
                     const int n = out_index<P, 1>(lane, b, r);
-                    xp[b * RL + r] = x[pl + n];
+                    xp[b * RL + r] = ld_nt(x + pl + n);
                     mp[b * RL + r] = medium(n);
-                    if constexpr (PF == 1) yp[b * RL + r] = y[pl + n];
+                    if constexpr (PF == 1) yp[b * RL + r] = ld_nt(y + pl + n);
                 }
         }
         fft_regs<P, 1, ROWS>(v, lds, ldp, col, lane, tw);
@@ -620,18 +640,18 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                 const int n = out_index<P, 1>(lane, b, r);
                 const int e = b * RL + r;
                 const cx<T> z = v[e];
-                const cx<T> xv = PF ? xp[PF ? e : 0] : ldg(x + pl + n);
+                const cx<T> xv = PF ? xp[PF ? e : 0] : ld_nt(x + pl + n);
                 const cx<T> dd = PF ? diag_m(n, mp[PF ? e : 0]) : diag(n);
                 if constexpr (MODE == CBS) {
                     const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
                     const cx<T> dxv = rmul(s.nu, cmul(bb, z - xv));
                     const cx<T> xn = xv + dxv;
-                    x[pl + n] = xn;
+                    st_nt(x + pl + n, xn);
                     acc0 += (double)norm2(dxv);
                     acc1 += (double)norm2(xv);
-                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : ldg(y + pl + n));
+                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : ld_nt(y + pl + n));
                 } else {
-                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : ldg(y + pl + n);
+                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : ld_nt(y + pl + n);
                     const cx<T> rr = yv - rmul(il, cmul(dd, xv)) - z;
                     w[pl + n] = rr;
                     acc0 += (double)norm2(rr);
