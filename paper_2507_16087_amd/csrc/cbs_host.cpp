@@ -1776,10 +1776,7 @@ namespace {
 cbs_status batch_geom(const cbs_grid* grid, Geom* g) {
     cbs_status vs = validate_grid(grid);
     if (vs != CBS_OK) return vs;
-    g->ndim = grid->ndim;
-    g->ncell = 1;
-    for (int d = 0; d < 3; ++d) g->n[d] = d < grid->ndim ? (int)grid->n[d] : 1;
-    for (int d = 0; d < grid->ndim; ++d) g->ncell *= g->n[d];
+    *g = geom_of(*grid);
     return CBS_OK;
 }
 
