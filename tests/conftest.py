@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def progress(msg: str) -> None:
     """Progress line for long GPU tests: straight to the terminal (past pytest's
-    output capture) and appended to gpurun_out/progress.log."""
+    output capture), and appended to the file CBS_PROGRESS_LOG names, if set."""
     import sys
     import time
     line = f"[{time.strftime('%H:%M:%S')}] {msg}"
@@ -24,9 +24,12 @@ def progress(msg: str) -> None:
         sys.__stderr__.flush()
     except Exception:
         pass
+    path = os.environ.get("CBS_PROGRESS_LOG")
+    if not path:
+        return
     try:
-        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-        with open(os.path.join(ROOT, "gpurun_out", "progress.log"), "a") as f:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "a") as f:
             f.write(line + "\n")
     except OSError:
         pass

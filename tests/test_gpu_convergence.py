@@ -5,7 +5,7 @@ recoverable, so the checks are self-consistent: the GPU needs exactly the
 oracle's iteration count for the same medium; more contrast (in c or in rho)
 needs more iterations; the minimum-enclosing-circle shift needs no more
 iterations than the component-wise median; a stronger absorbing layer slows
-convergence.  The measured table is printed (pytest -s) and kept in the design doc.
+convergence.  The measured table is printed (pytest -s).
 """
 import numpy as np
 import pytest
