@@ -29,8 +29,8 @@
  *  - adjoint operator A^H (Sec. 2.3): the negated differential part plus the
  *    conjugated diagonal.
  *
- * Readings where the paper is silent or inconsistent (listed in the design
- * notes): hat-sources s_p*q and rhobar*s_u; absorbing layer
+ * Readings where the paper is silent or inconsistent: hat-sources s_p*q and
+ * rhobar*s_u; absorbing layer
  * gamma = gmax * sum_eta r_eta^2 with r the periodic distance into the layer
  * over (L + 1/2); periodic wrap of the density average; scale floor
  * lam >= 1e-3 |a|; stopping test skipped at the first iteration.
