@@ -16,6 +16,8 @@ Prints one JSON line.  Fields beyond the driver contract:
   cpu_baseline     -- the FP64 oracle on a bounded sample of the same workload
   pressure_rel_diff_refined_vs_fp64 -- relative L2 distance of the two solves'
                       pressure fields (both stopped at the same FP64 residual)
+  medium_setup_s   -- host planning and upload of the medium (outside the timed region)
+  serving, p50_ms, p99_ms -- the request-stream leg (mixed sizes, continuous batching)
 """
 from __future__ import annotations
 
