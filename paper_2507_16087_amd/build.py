@@ -1,6 +1,8 @@
 """Compile the gfx950 solver library (libcbs.so) in-tree with hipcc.
 
-Every translation unit is built for gfx950 only, with packed-FP32 ALU
+The FFT pass kernels are compiled once per plan group (the axis lengths are
+spread over several objects so the builds run in parallel).  Every
+translation unit is built for gfx950 only, with packed-FP32 ALU
 instructions disabled, then linked into one shared library that exports the C
 ABI of include/cbs.h.  ``python -m paper_2507_16087_amd.build`` or
 ``paper_2507_16087_amd.build.build()``.
@@ -21,16 +23,22 @@ LIB = os.path.join(PKG, "libcbs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cbs_kernels.hip", "cbs_host.cpp"]
+# the FFT pass kernels, one object per plan group (see csrc/cbs_plans.h)
+PLAN_GROUPS = 8
+GROUP_SRC = "cbs_pass_group.hip"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument",
           "-I", INCLUDE, "-I", CSRC]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJDIR, src + ".o")
+def _compile(job, verbose: bool) -> str:
+    src, group = job
+    tag = src if group is None else f"{src}.g{group}"
+    obj = os.path.join(OBJDIR, tag + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    defs = [] if group is None else [f"-DCBS_GROUP={group}"]
+    cmd = [HIPCC] + COMMON + defs + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,8 +52,10 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    jobs = [(GROUP_SRC, g) for g in range(PLAN_GROUPS)] + [(s, None) for s in SOURCES]
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda j: _compile(j, verbose), jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:

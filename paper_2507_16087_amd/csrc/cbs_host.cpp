@@ -65,13 +65,8 @@ using namespace cbs;
 
 namespace {
 
-const int kSizes[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512};
-
-bool size_supported(int64_t n) {
-    for (int s : kSizes)
-        if (s == n) return true;
-    return false;
-}
+// Axis lengths with a compiled FFT plan: every 2^a 3^b in [4, 512].
+bool size_supported(int64_t n) { return n >= 4 && n <= 512 && plan_tpc((int)n, false) > 0; }
 
 // ----------------------------------------------------------- pass config --
 // The passes of one iteration, and the column-tile width of each.

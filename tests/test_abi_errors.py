@@ -45,12 +45,33 @@ def test_invalid_medium_values(bad):
 
 
 @pytest.mark.parametrize("n,code", [((10, 16, 16), L.CBS_E_UNSUPPORTED), ((16, 7, 16), L.CBS_E_UNSUPPORTED),
-                                    ((1024, 16, 16), L.CBS_E_UNSUPPORTED), ((384, 8, 8), L.CBS_E_UNSUPPORTED)])
+                                    ((1024, 16, 16), L.CBS_E_UNSUPPORTED), ((768, 16, 16), L.CBS_E_UNSUPPORTED),
+                                    ((16, 16, 2), L.CBS_E_UNSUPPORTED), ((16, 20, 16), L.CBS_E_UNSUPPORTED)])
 def test_unsupported_sizes(n, code):
     shape = n
     ones = np.ones(shape)
     st, h = _create(_grid(n), ones * 1500, ones * 1000, ones * 0)
     assert st == code
+
+
+SMOOTH = [a * b for a in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512) for b in (1, 3, 9, 27, 81, 243)
+          if 4 <= a * b <= 512]
+
+
+def test_every_smooth_length_is_accepted():
+    """Every axis length 2^a 3^b in [4, 512] has a plan (the host planner runs
+    its size checks without a device); 5, 7 and their multiples do not."""
+    from paper_2507_16087_amd import solver
+    assert len(SMOOTH) == 31
+    for n in SMOOTH:
+        shape = (n, 4)
+        ones = np.ones(shape)
+        s = solver.plan_scalars(shape, 1e-4, 6e6, ones * 1500, ones * 1000, ones * 0, pml=1)
+        assert s["lam1"] > 0, n
+    for n in (5, 10, 14, 20, 40, 100, 1024):
+        ones = np.ones((n, 4))
+        with pytest.raises(Exception):
+            solver.plan_scalars((n, 4), 1e-4, 6e6, ones * 1500, ones * 1000, ones * 0, pml=1)
 
 
 @pytest.mark.parametrize("kw", [dict(pml=8), dict(pml=-1), dict(beta=-0.5), dict(nu=float("nan")),
