@@ -15,8 +15,10 @@
  *
  * Conventions shared by every entry point
  *  - Grid: ndim in {2, 3}; n[eta] cells per axis, C order, last axis
- *    contiguous.  Each n[eta] must be one of 4, 6, 8, 12, 16, 24, 32, 48, 64,
- *    96, 128, 192, 256, 512 (else CBS_E_UNSUPPORTED).  Cell centres sit at integer
+ *    contiguous.  Each n[eta] must be of the form 2^a 3^b with
+ *    4 <= n[eta] <= 512 (4, 6, 8, 9, 12, 16, 18, 24, 27, ..., 384, 432, 486,
+ *    512: one compiled FFT plan per length, a whole pencil in one
+ *    work-group), else CBS_E_UNSUPPORTED.  Cell centres sit at integer
  *    multiples of dx; u_eta sits half a cell further along eta.
  *  - Units: SI.  alpha in Np/m, omega in rad/s.
  *  - Media c, rho, alpha: real float64 arrays of prod(n) cells.  c > 0,
