@@ -2,7 +2,13 @@
 
 Requests (a grid, a frequency, a medium and a source) arrive over time.  Each
 is admitted when its HBM footprint fits the budget and a slot of its grid
-shape is free; admitted requests are planned (medium setup, on a host thread
+shape is free (:class:`Admission`: requests of one shape keep their arrival
+order, but a shape whose pool is full or whose request does not fit yet does
+not hold back requests of other shapes; a request that could never fit the
+budget is closed with an error; idle pools of other shapes give their
+workspace back when memory is short; and a request blocked on memory longer
+than ``max_wait_s`` stops later requests from taking memory until it is
+admitted).  Admitted requests are planned (medium setup, on a host thread
 pool) and submitted as slots of a per-shape :class:`solver.Batch`.  Every
 shape pool runs on its own HIP stream and host thread, advancing all of its
 active slots together (one kernel launch per pass covers every slot) a fixed
@@ -22,13 +28,96 @@ import dataclasses
 import queue
 import threading
 import time
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
 from . import solver
 
 MEDIUM_BYTES_PER_CELL = 8 * 3 + 16 + 4 * 3 + 8 + 8 * 3   # rhobar, q (FP64, FP32), c, rho, alpha
+
+
+@dataclasses.dataclass
+class _PoolState:
+    reserved: int = 0       # admitted requests of this shape not finished yet
+    ws_bytes: int = 0       # the pool's batch workspace
+
+
+class Admission:
+    """Admission by HBM footprint, without a device (the server drives it).
+
+    State: the byte budget, the bytes in use (media of admitted requests plus
+    the workspace of every open pool) and, per shape, the requests admitted
+    and not yet finished.  :meth:`select` walks the pending requests in
+    arrival order and decides, for each, one of:
+
+    * admit -- its pool has a free slot and its footprint (medium, plus the
+      pool's workspace if the pool is not open yet) fits the free budget,
+      after closing idle pools of other shapes (oldest first) if needed;
+    * fail -- its footprint exceeds the whole budget, so it could never run;
+    * wait -- otherwise.  Later requests of the same shape wait too (one
+      FIFO per shape); other shapes are still considered, unless this request
+      has waited on memory for more than ``max_wait_s``, in which case the
+      walk stops so that it is the next to get memory.
+    """
+
+    def __init__(self, budget: int, slots_per_pool: int, max_wait_s: float,
+                 medium_bytes: Callable[[tuple], int], pool_bytes: Callable[[tuple], int]):
+        self.budget, self.slots, self.max_wait = int(budget), int(slots_per_pool), float(max_wait_s)
+        self.medium_bytes, self.pool_bytes = medium_bytes, pool_bytes
+        self.used = 0
+        self.pools: Dict[tuple, _PoolState] = {}     # open pools, oldest first
+        self.memory_waits = 0                        # requests that waited on memory at least once
+        self._waited: set = set()
+        self.evictions = 0
+
+    def select(self, pending, now: float):
+        """pending: objects with .shape, .arrival, .rid in arrival order.
+        Returns (admitted, failed, evicted shapes); the state is updated for
+        the admitted requests and the closed pools."""
+        admitted, failed, evicted = [], [], []
+        blocked = set()
+        for req in pending:
+            shape = req.shape
+            if shape in blocked:
+                continue
+            med, ws = self.medium_bytes(shape), self.pool_bytes(shape)
+            if med + ws > self.budget:
+                failed.append(req)
+                continue
+            pool = self.pools.get(shape)
+            if pool is not None and pool.reserved >= self.slots:
+                blocked.add(shape)
+                continue
+            need = med + (0 if pool is not None else ws)
+            if self.used + need > self.budget:
+                for other, st in list(self.pools.items()):
+                    if self.used + need <= self.budget:
+                        break
+                    if other != shape and st.reserved == 0:
+                        self.used -= st.ws_bytes
+                        del self.pools[other]
+                        evicted.append(other)
+                        self.evictions += 1
+            if self.used + need > self.budget:
+                blocked.add(shape)
+                if req.rid not in self._waited:
+                    self._waited.add(req.rid)
+                    self.memory_waits += 1
+                if now - req.arrival > self.max_wait:
+                    break
+                continue
+            if pool is None:
+                pool = self.pools[shape] = _PoolState(ws_bytes=ws)
+            pool.reserved += 1
+            self.used += need
+            admitted.append(req)
+        return admitted, failed, evicted
+
+    def release(self, shape) -> None:
+        """A request of this shape finished (or failed after admission)."""
+        self.pools[shape].reserved -= 1
+        self.used -= self.medium_bytes(shape)
 
 
 @dataclasses.dataclass
@@ -106,7 +195,7 @@ class Server:
 
     def __init__(self, prec="fp32_refined", tol=1e-5, inner_tol=0.0, slots_per_pool=4,
                  step_iters=32, hbm_budget: Optional[int] = None, plan_workers=4,
-                 keep_fields=False):
+                 keep_fields=False, max_wait_s: float = 5.0):
         import torch
         self.prec, self.tol, self.inner_tol = prec, tol, inner_tol
         self.slots_per_pool, self.step_iters = slots_per_pool, step_iters
@@ -114,7 +203,9 @@ class Server:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = int(0.8 * free)
         self.budget = hbm_budget
-        self.used = 0
+        self._ws_bytes: Dict[tuple, int] = {}
+        self.adm = Admission(hbm_budget, slots_per_pool, max_wait_s, self._medium_bytes,
+                             self._pool_bytes)
         self.keep_fields = keep_fields
         self.pools: Dict[tuple, _Pool] = {}
         self.results: Dict[int, Result] = {}
@@ -123,6 +214,10 @@ class Server:
         self.planner = cf.ThreadPoolExecutor(max_workers=plan_workers)
         self.timeline: List[tuple] = []   # (time, active solves)
         self.active = 0
+
+    @property
+    def used(self) -> int:
+        return self.adm.used
 
     # -- accounting -------------------------------------------------------
     def _mark(self, rid, what):
@@ -139,8 +234,7 @@ class Server:
             r.error = error
             if self.keep_fields:
                 r.p = p
-            pool.reserved -= 1
-            self.used -= self._medium_bytes(pool.shape)
+            self.adm.release(pool.shape)
             self.active -= 1
             self.timeline.append((r.done, self.active))
             self.cv.notify_all()
@@ -154,11 +248,10 @@ class Server:
     def _medium_bytes(shape):
         return int(np.prod(shape)) * MEDIUM_BYTES_PER_CELL
 
-    def footprint(self, shape, new_pool: bool) -> int:
-        """HBM bytes admitting one request of this shape needs now."""
-        need = self._medium_bytes(shape)
-        if new_pool:
-            b = solver.L.lib()
+    def _pool_bytes(self, shape) -> int:
+        """Workspace of a pool of this shape (slots_per_pool solves)."""
+        shape = tuple(shape)
+        if shape not in self._ws_bytes:
             import ctypes as C
             g = solver.L.Grid()
             g.ndim = len(shape)
@@ -166,31 +259,28 @@ class Server:
                 g.n[d] = shape[d] if d < len(shape) else 1
             g.dx, g.omega = 1.0, 1.0
             nb = C.c_size_t()
-            solver.L.check(b.cbs_batch_workspace_bytes(C.byref(g), solver.PREC[self.prec],
-                                                       self.slots_per_pool, C.byref(nb)),
-                           "cbs_batch_workspace_bytes")
-            need += nb.value
-        return need
+            solver.L.check(solver.L.lib().cbs_batch_workspace_bytes(
+                C.byref(g), solver.PREC[self.prec], self.slots_per_pool, C.byref(nb)),
+                "cbs_batch_workspace_bytes")
+            self._ws_bytes[shape] = nb.value
+        return self._ws_bytes[shape]
+
+    def footprint(self, shape, new_pool: bool) -> int:
+        """HBM bytes admitting one request of this shape needs now."""
+        return self._medium_bytes(shape) + (self._pool_bytes(shape) if new_pool else 0)
 
     # -- admission --------------------------------------------------------
-    def _try_admit(self, req) -> bool:
+    def _start(self, req):
+        """Open the request's pool if needed and plan its medium."""
         pr = req.problem
-        shape = pr.shape
-        with self.lock:
-            pool = self.pools.get(shape)
-            if pool is not None and pool.reserved >= self.slots_per_pool:
-                return False
-            need = self.footprint(shape, pool is None)
-            if self.used + need > self.budget:
-                return False
-            self.used += need
-            if pool is None:
-                pool = _Pool(self, shape, pr.dx)
-                self.pools[shape] = pool
-            pool.reserved += 1
-            self.active += 1
-            self.timeline.append((time.perf_counter(), self.active))
-            self.results[req.rid].admitted = time.perf_counter()
+        pool = self.pools.get(pr.shape)
+        if pool is None:
+            pool = _Pool(self, pr.shape, pr.dx)
+            self.pools[pr.shape] = pool
+        self.active += 1
+        now = time.perf_counter()
+        self.timeline.append((now, self.active))
+        self.results[req.rid].admitted = now
 
         def plan():
             try:
@@ -201,24 +291,44 @@ class Server:
             pool.inbox.put((req.rid, m, pr.dense_source().ravel()))
 
         self.planner.submit(plan)
-        return True
+
+    def _close_pool(self, shape):
+        """Stop an idle pool's thread and drop its batch (workspace)."""
+        pool = self.pools.pop(shape)
+        pool.stop = True
+        pool.thread.join()
+        del pool.batch
 
     def run(self, requests, time_scale: float = 1.0) -> dict:
         """Replay `requests` (arrival_s relative to start, divided by
         time_scale) and return per-request results and latency statistics."""
         reqs = sorted(requests, key=lambda r: r.arrival_s)
         t0 = time.perf_counter()
-        pending: List = []
+        pending: List[_Pending] = []
         i = 0
         for r in reqs:
             self.results[r.rid] = Result(r.rid, r.problem.shape, t0 + r.arrival_s / time_scale)
         while True:
             now = time.perf_counter()
             while i < len(reqs) and t0 + reqs[i].arrival_s / time_scale <= now:
-                pending.append(reqs[i])
+                rq = reqs[i]
+                pending.append(_Pending(rq.rid, rq.problem.shape, self.results[rq.rid].arrival, rq))
                 i += 1
-            while pending and self._try_admit(pending[0]):
-                pending.pop(0)
+            if pending:
+                with self.lock:
+                    admitted, failed, evicted = self.adm.select(pending, now)
+                for shape in evicted:
+                    self._close_pool(shape)
+                with self.cv:
+                    for pq in admitted:
+                        self._start(pq.req)
+                    for pq in failed:
+                        r = self.results[pq.rid]
+                        r.done = time.perf_counter()
+                        r.error = "footprint exceeds the HBM budget"
+                    self.cv.notify_all()
+                gone = {id(pq) for pq in admitted + failed}
+                pending = [pq for pq in pending if id(pq) not in gone]
             with self.cv:
                 if i == len(reqs) and not pending and all(r.done > 0 for r in self.results.values()):
                     break
@@ -234,8 +344,24 @@ class Server:
         res = [self.results[r.rid] for r in reqs]
         lat = np.array([r.latency for r in res]) * 1e3
         span = max(r.done for r in res) - t0
+        by_size = {}
+        for shape in sorted({r.shape for r in res}):
+            ls = np.array([r.latency for r in res if r.shape == shape]) * 1e3
+            by_size["x".join(map(str, shape))] = dict(
+                count=int(ls.size), p50_ms=float(np.percentile(ls, 50)),
+                p99_ms=float(np.percentile(ls, 99)))
         return dict(results=res, p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), solves_per_s=len(res) / span,
                     wall_s=span, max_concurrency=max((a for _, a in self.timeline), default=0),
                     converged=sum(r.converged for r in res),
-                    failed=sum(r.error is not None for r in res))
+                    failed=sum(r.error is not None for r in res),
+                    by_size=by_size, budget_bytes=self.budget,
+                    memory_waits=self.adm.memory_waits, pool_evictions=self.adm.evictions)
+
+
+@dataclasses.dataclass
+class _Pending:
+    rid: int
+    shape: tuple
+    arrival: float
+    req: object

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2507_16087_amd import workloads as W
+from parity_util import maxrel, rel
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -35,7 +36,9 @@ def _medium(cbs, pr):
 
 
 def _rel(a, b):
-    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+    """Error measure of the parity checks: the larger of the relative L2 error
+    and the largest element-wise error over the largest reference modulus."""
+    return max(rel(a, b), maxrel(a, b))
 
 
 @pytest.mark.parametrize("prec", ["fp32_refined", "fp64"])
@@ -142,3 +145,33 @@ def test_concurrent_solves_on_one_medium(cbs):
     for p, it in out:
         assert it == iref["iterations"]
         assert _rel(p, ref.cpu().numpy()) <= 1e-12
+
+
+def test_small_request_passes_a_blocked_large_one(cbs):
+    """One slot per pool: a second 96^3 request waits for the first one's slot,
+    but a 24^3 request arriving after it is admitted at once (its pool has a
+    free slot and it fits the budget) and finishes before either 96^3 one."""
+    from paper_2507_16087_amd.serve import Server
+    big0, big1 = _prob(96, 1e6, 301), _prob(96, 1e6, 302)
+    small = _prob(24, 1e6, 303)
+    reqs = [W.Request(0, 0.0, big0), W.Request(1, 0.001, big1), W.Request(2, 0.002, small)]
+    out = Server(tol=1e-6, slots_per_pool=1, step_iters=16).run(reqs)
+    assert out["converged"] == 3
+    r = {x.rid: x for x in out["results"]}
+    assert r[2].admitted < r[1].admitted
+    assert r[2].done < r[0].done and r[2].done < r[1].done
+    assert out["by_size"]["24x24x24"]["count"] == 1
+
+
+def test_request_larger_than_the_budget_is_closed(cbs):
+    """A budget that holds one 24^3 pool and medium but not a 48^3 one: the
+    48^3 request is closed with an error at once and the others complete."""
+    from paper_2507_16087_amd.serve import Server
+    probe = Server(tol=1e-6, slots_per_pool=2)
+    budget = probe.footprint((24, 24, 24), True) + 2 * Server._medium_bytes((24, 24, 24))
+    assert probe.footprint((48, 48, 48), True) > budget
+    reqs = [W.Request(0, 0.0, _prob(24, 1e6, 311)), W.Request(1, 0.0, _prob(48, 1e6, 312)),
+            W.Request(2, 0.0, _prob(24, 1e6, 313))]
+    out = Server(tol=1e-6, slots_per_pool=2, hbm_budget=budget).run(reqs)
+    assert out["converged"] == 2 and out["failed"] == 1
+    assert "budget" in out["results"][1].error
