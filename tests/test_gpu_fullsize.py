@@ -6,13 +6,18 @@ benchmark times (autotuned plans of the same shapes).
 * 256^3 skull-like shell (the benchmark workload): FP64 iterates after 2
   iterations against the oracle's on sampled cells and pencils, <= 1e-10;
   the refined-FP32 solution's scaled residual evaluated by the oracle's own
-  operator equals the GPU-reported one; the refined solution at tol 1e-6 is
-  within 1e-5 of the FP64 GPU solution converged to a residual of 1e-9.
+  operator equals the GPU-reported one; the refined solution at a scaled
+  residual of 1e-7 is within 1e-5 of the FP64 GPU solution at 1e-8.  The
+  FP64 GPU path stands in for a converged oracle here: the oracle's own
+  256^3 solve would need some 40 000 iterations at seconds each on the host,
+  so its contact at this size is iterate parity (here and, after a few
+  hundred iterations, in test_gpu_oracle_refs.py) and the residual check.
 """
 import numpy as np
 import pytest
 
 from paper_2507_16087_amd import workloads as W
+from parity_util import maxrel, rel
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -27,7 +32,9 @@ def cbs():
 
 
 def _rel(a, b):
-    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+    """Error measure of the parity checks: the larger of the relative L2 error
+    and the largest element-wise error over the largest reference modulus."""
+    return max(rel(a, b), maxrel(a, b))
 
 
 def test_random128_fp64_iterates(cbs, orc):
@@ -78,9 +85,9 @@ def test_shell256_fp64_iterates_sampled(cbs, shell, report):
 def test_shell256_refined_accuracy(cbs, shell, report):
     """The skull-like case is ill-conditioned: the error is ~40x the scaled
     residual, for FP64 and refined FP32 alike.  A 1e-5 error therefore needs a
-    residual of ~1e-7; both paths are solved to 1e-7 and compared with the
-    FP64 solution at 1e-8 (error <= ~4e-7, 25x below the gate; FP64 itself is
-    iterate-pinned to the oracle above)."""
+    residual of ~1e-7; the refined path is solved to 1e-7 and compared with
+    the FP64 solution at 1e-8 (error <= ~4e-7, 25x below the gate; FP64
+    itself is iterate-pinned to the oracle)."""
     import torch
     from paper_2507_16087_amd import _lib
     pr, gm, om = shell
@@ -99,13 +106,10 @@ def test_shell256_refined_accuracy(cbs, shell, report):
     report("shell3d 256^3: FP64 reference solve to 1e-8")
     ref, _, iref = cbs.solve(gm, sp, tol=1e-8, prec="fp64", max_iter=400000, check_every=200,
                              stop_rule=_lib.CBS_STOP_RESIDUAL, want_u=False)
-    report(f"  {iref['iterations']} iterations; FP64 solve to 1e-7")
+    report(f"  {iref['iterations']} iterations")
     assert iref["converged"]
-    p64, _, i64 = cbs.solve(gm, sp, tol=1e-7, prec="fp64", max_iter=400000, check_every=50,
-                            stop_rule=_lib.CBS_STOP_RESIDUAL, want_u=False)
-    report(f"  {i64['iterations']} iterations")
     e32 = (torch.linalg.norm(p32 - ref) / torch.linalg.norm(ref)).item()
-    e64 = (torch.linalg.norm(p64 - ref) / torch.linalg.norm(ref)).item()
-    print(f"256^3 shell at residual 1e-7: refined FP32 error {e32:.2e} "
-          f"({i32['iterations']} it), FP64 error {e64:.2e} ({i64['iterations']} it)")
-    assert e32 <= 1e-5, (e32, e64)
+    m32 = (torch.abs(p32 - ref).max() / torch.abs(ref).max()).item()
+    print(f"256^3 shell at residual 1e-7: refined FP32 pressure error {e32:.2e} (max-abs {m32:.2e}, "
+          f"{i32['iterations']} it) against FP64 at 1e-8 ({iref['iterations']} it)")
+    assert e32 <= 1e-5 and m32 <= 1e-5, (e32, m32)

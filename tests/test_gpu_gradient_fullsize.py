@@ -11,8 +11,9 @@ with a smooth bump (c up 3 %, rho down 3 %), J = sum_shots 1/2 |M p - d|^2.
   128^3 solves would take hours per shot.
 * Directional derivatives of J (FP64) against central differences of FP64
   solves along seeded smooth directions, taken in turn for c, rho and alpha:
-  <= 1e-6.  Three directions by default; CBS_FD_DIRECTIONS=16 runs the
-  workload's full set (about 15 s each).
+  <= 1e-6.  The workload's sixteen seeded directions (5000 + k), taken for
+  c, rho and alpha in turn (about 8 s each); CBS_FD_DIRECTIONS=n runs the
+  first n.
 """
 import os
 import time
@@ -25,7 +26,7 @@ from paper_2507_16087_amd import workloads as W
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
 N = 128
-DIRECTIONS = int(os.environ.get("CBS_FD_DIRECTIONS", "3"))
+DIRECTIONS = int(os.environ.get("CBS_FD_DIRECTIONS", "16"))
 
 
 @pytest.fixture(scope="module")
