@@ -224,18 +224,20 @@ cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
  * out[4 i + 0..3] = kind, axis length, columns per work-group and flags of
  * pass i in launch order (kind -1 = unused).  Flags:
  *   bit 0     wide radix split (fewer elements per thread);
- *   bits 1-3  variant.  Propagator pass: LDS layout 0 one tile reused field
+ *   bits 1-4  variant.  Propagator pass: LDS layout 0 one tile reused field
  *             by field, 1 one region per field with every exchange shared,
  *             2 two regions with fields in pairs, plus 4 for a column tile
  *             without row padding.  Strided passes: 4 = no row padding.
  *             Last-axis inverse pass: prefetch 0 none, 1 x, y and the medium
  *             issued before the transform, 2 x and the medium;
- *   bits 4+   (3-D middle passes) the number of last-axis column blocks the
+ *   bits 5+   (3-D middle passes) the number of last-axis column blocks the
  *             forward-axis-1, propagator and inverse-axis-1 passes run in,
  *             one block after the other so a block's data is still in the
  *             memory-side cache for its next pass (1 = whole grid).
  * The first solve of each (shape, precision) in a process times the
  * candidate plans and block counts on its workspace and keeps the fastest.
+ * Axis lengths other than powers of two and three times powers of two (9, 18, 27, ...)
+ * have only variant 0 of each pass (and the unpadded column tile).
  * Environment: CBS_AUTOTUNE=0 keeps the defaults; CBS_PROP_VARIANT (0, 1, 2,
  * 4, 5, 6), CBS_LAST_VARIANT (0, 1, 2), CBS_STRIDED_VARIANT (0, 4) and
  * CBS_COLUMN_BLOCKS (1, 2, 4, 8) pin a choice, tuned or not; CBS_TUNE_FILE

@@ -13,6 +13,7 @@ import concurrent.futures as cf
 import os
 import subprocess
 import sys
+import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -24,7 +25,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cbs_kernels.hip", "cbs_host.cpp"]
 # the FFT pass kernels, one object per plan group (see csrc/cbs_plans.h)
-PLAN_GROUPS = 8
+PLAN_GROUPS = 11
 GROUP_SRC = "cbs_pass_group.hip"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -41,7 +42,10 @@ def _compile(job, verbose: bool) -> str:
     cmd = [HIPCC] + COMMON + defs + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
+    t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
+    if verbose:
+        print(f"{tag}: {time.time() - t0:.1f} s", flush=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
     warn = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]

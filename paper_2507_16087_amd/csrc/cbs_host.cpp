@@ -32,6 +32,8 @@ hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, con
 template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st);
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st);
+hipError_t launch_pencil_flags(const cx<double>* plane, int64_t pencils, int n, unsigned char* flag,
+                               hipStream_t st);
 template <typename T>
 hipError_t launch_zero(cx<T>* p, int64_t n, hipStream_t st);
 hipError_t launch_rhs(const Geom& g, const cx<double>* sp, const cx<double>* su, const double* rhobar,
@@ -53,6 +55,7 @@ hipError_t launch_gradient(const Geom& g, const double* c, const double* rho, co
                            double* grho, double* galpha, int collocated, hipStream_t st);
 int plan_tpc(int n, bool wide);
 bool plan_has_wide(int n);
+bool plan_has_variants(int n);
 enum { MODE_CBS = 0, MODE_APPLY = 1 };
 }  // namespace cbs
 
@@ -98,6 +101,23 @@ int pow2_floor_div(int64_t total, int cap) {
     return p;
 }
 
+// The default pass along the contiguous last axis (kind 0 forward with the
+// prologue, 1 inverse with the epilogue).
+Pass contig_pass(const Geom& g, int kind, bool fp64) {
+    Pass p{};
+    p.kind = kind;
+    p.axis = g.ndim - 1;
+    p.n = g.n[p.axis];
+    p.wide = false;
+    const int tpc = std::max(1, plan_tpc(p.n, false));
+    const int64_t pencils = g.ncell / g.n[p.axis];
+    // whole pencils per work-group: at most 256 threads and ~40 KiB of LDS
+    const size_t pencil_lds = (size_t)(p.n + p.n / 16) * (fp64 ? 16 : 8);
+    const int lds_cap = (int)std::max<size_t>(1, (40 * 1024) / pencil_lds);
+    p.pcols = pow2_floor_div(pencils, std::min(256 / tpc, lds_cap));
+    return p;
+}
+
 PassSet make_passes(const Geom& g, bool fp64) {
     PassSet ps{};
     const int last = g.ndim - 1;
@@ -108,24 +128,11 @@ PassSet make_passes(const Geom& g, bool fp64) {
         p.axis = axis;
         p.n = g.n[axis];
         p.wide = wide && plan_has_wide(p.n);
-        const int tpc = plan_tpc(p.n, p.wide);
+        const int tpc = std::max(1, plan_tpc(p.n, p.wide));   // every length here has a plan
         p.pcols = pow2_floor_div(g.n[last], std::min(pstr, 256 / tpc));
         return p;
     };
-    auto contig = [&](int kind) {
-        Pass p{};
-        p.kind = kind;
-        p.axis = last;
-        p.n = g.n[last];
-        p.wide = false;
-        const int tpc = plan_tpc(p.n, false);
-        const int64_t pencils = g.ncell / g.n[last];
-        // whole pencils per work-group: at most 256 threads and ~40 KiB of LDS
-        const size_t pencil_lds = (size_t)(p.n + p.n / 16) * (fp64 ? 16 : 8);
-        const int lds_cap = (int)std::max<size_t>(1, (40 * 1024) / pencil_lds);
-        p.pcols = pow2_floor_div(pencils, std::min(256 / tpc, lds_cap));
-        return p;
-    };
+    auto contig = [&](int kind) { return contig_pass(g, kind, fp64); };
     int k = 0;
     ps.p[k++] = contig(0);
     if (g.ndim == 3) ps.p[k++] = strided(2, 1, false);
@@ -475,9 +482,11 @@ void timing_harvest(PassTiming& t) {
 // Passes of one iteration for a set of same-shape slots.  In CBS mode the
 // stand-alone prologue pass runs only over `starts` (slots whose CBS run
 // begins with this iteration); the other passes run over `all`.
+// yflags: OR-ed into the variant of the last-axis launches (16: the slots'
+// right-hand side is sparse, see Slot::ypen).
 template <typename T>
 hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int mode, const Slot<T>* all,
-                          int nall, const Slot<T>* starts, int nstart, hipStream_t st) {
+                          int nall, const Slot<T>* starts, int nstart, hipStream_t st, int yflags = 0) {
     const bool timed = tp && tp->on;
     const int group = mode == MODE_APPLY ? 2 : (sizeof(T) == 8 ? 1 : 0);
     auto launch = [&](int i, int l0, int lw) -> hipError_t {
@@ -487,8 +496,9 @@ hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int 
         const int slot = i == ps.count - 1 ? 4 : i;
         const bool ev = timed && ((tp->mask >> slot) & 1);
         if (ev && timing_begin(*tp, group * 8 + slot, st) != hipSuccess) return hipErrorUnknown;
+        const int variant = (p.kind == 0 || p.kind == 1) ? (p.variant | yflags) : p.variant;
         hipError_t e = launch_pass<T>(kind, mode, pro ? starts : all, pro ? nstart : nall, g, p.axis, p.n, p.pcols,
-                                      p.wide, p.variant, st, l0, lw);
+                                      p.wide, variant, st, l0, lw);
         if (e != hipSuccess) return e;
         if (ev && timing_end(*tp, st) != hipSuccess) return hipErrorUnknown;
         return hipSuccess;
@@ -516,8 +526,8 @@ hipError_t run_passes_set(const Geom& g, PassTiming* tp, const PassSet& ps, int 
 
 template <typename T>
 hipError_t run_passes(cbs_medium_s* m, const PassSet& ps, int mode, const Slot<T>* dslots, int nslots,
-                      hipStream_t st, bool start = true) {
-    return run_passes_set<T>(m->g, &m->timing, ps, mode, dslots, nslots, dslots, start ? nslots : 0, st);
+                      hipStream_t st, bool start = true, int yflags = 0) {
+    return run_passes_set<T>(m->g, &m->timing, ps, mode, dslots, nslots, dslots, start ? nslots : 0, st, yflags);
 }
 
 // ------------------------------------------------------------ autotuner --
@@ -541,9 +551,10 @@ struct TuneKey {
 // pairs); the last-axis inverse pass's prefetch (0 none, 1 x, y and medium,
 // 2 x and medium).  Bit 2 of a strided or propagator variant drops the
 // one-element row padding of the column tile.
-std::vector<int> variants_of(int kind) {
-    if (kind == 4) return {0, 1, 2, 4, 5, 6};
-    if (kind == 1) return {0, 1, 2};
+std::vector<int> variants_of(int kind, int n) {
+    const bool all = plan_has_variants(n);   // else only variant 0 is compiled
+    if (kind == 4) return all ? std::vector<int>{0, 1, 2, 4, 5, 6} : std::vector<int>{0, 4};
+    if (kind == 1) return all ? std::vector<int>{0, 1, 2} : std::vector<int>{0};
     if (kind == 2 || kind == 3) return {0, 4};
     return {0};
 }
@@ -551,13 +562,26 @@ std::vector<int> variants_of(int kind) {
 // CBS_PROP_VARIANT pins the propagator pass, CBS_LAST_VARIANT the last-axis
 // inverse pass and CBS_STRIDED_VARIANT the strided passes to one of their
 // variants; unset, all compete.
-int forced_variant(int kind) {
+// The raw pin of a pass kind from the environment (-1 unset), before any
+// check against a length's plans: part of the tuning cache key.
+int env_pin(int kind) {
     const char* name = kind == 4 ? "CBS_PROP_VARIANT" : (kind == 1 ? "CBS_LAST_VARIANT" : "CBS_STRIDED_VARIANT");
     const char* e = std::getenv(name);
-    if (!e || e[0] < '0' || e[0] > '9' || e[1] != 0) return -1;
-    const int v = e[0] - '0';
-    for (int ok : variants_of(kind))
-        if (ok == v) return v;
+    if (!e || e[0] < '0' || e[0] > '9') return -1;
+    char* end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    return (end && *end == 0 && v < 64) ? (int)v : -1;
+}
+
+int forced_variant(int kind, int n) {
+    const char* name = kind == 4 ? "CBS_PROP_VARIANT" : (kind == 1 ? "CBS_LAST_VARIANT" : "CBS_STRIDED_VARIANT");
+    const char* e = std::getenv(name);
+    if (!e || e[0] < '0' || e[0] > '9') return -1;
+    char* end = nullptr;
+    const long v = std::strtol(e, &end, 10);
+    if (!end || *end != 0) return -1;
+    for (int ok : variants_of(kind, n))
+        if (ok == v) return (int)v;
     return -1;
 }
 std::mutex g_tune_mu;
@@ -610,8 +634,8 @@ std::vector<Pass> pass_candidates(const Geom& g, const Pass& base, bool fp64) {
             Pass p = base;
             p.wide = wide != 0;
             p.pcols = pc;
-            const int pinned = forced_variant(base.kind);
-            for (int v : variants_of(base.kind)) {
+            const int pinned = forced_variant(base.kind, base.n);
+            for (int v : variants_of(base.kind, base.n)) {
                 if (pinned >= 0 && v != pinned) continue;
                 p.variant = v;
                 out.push_back(p);
@@ -727,7 +751,7 @@ cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T
 }
 
 struct Layout {
-    size_t off_slot64, off_ctl64, off_part64, off_chunk64, off_x64, off_w64, off_y64;
+    size_t off_slot64, off_ctl64, off_part64, off_chunk64, off_x64, off_w64, off_y64, off_ypen64;
     size_t off_slot32, off_ctl32, off_part32, off_chunk32, off_d32, off_w32, off_y32;
     size_t total;
 };
@@ -751,6 +775,7 @@ Layout layout_for(const Geom& g, int prec) {
     L.off_x64 = take(nf * sizeof(cx<double>));
     L.off_w64 = take(nf * sizeof(cx<double>));
     L.off_y64 = take(nf * sizeof(cx<double>));
+    L.off_ypen64 = take((size_t)(g.ncell / g.n[g.ndim - 1]));   // pencil flags of a sparse y
     if (prec == CBS_FP32_REFINED) {
         L.off_slot32 = take(sizeof(Slot<float>));
         L.off_ctl32 = take(sizeof(Ctl));
@@ -819,7 +844,7 @@ bool plausible(const Geom& g, const PassSet& def, const PassSet& ps) {
         if (p.pcols < 1 || (p.pcols & (p.pcols - 1)) || tpc <= 0 || p.pcols * tpc > 256) return false;
         const int64_t total = (p.kind == 0 || p.kind == 1) ? g.ncell / g.n[last] : g.n[last];
         if (total % p.pcols) return false;
-        const std::vector<int> vs = variants_of(p.kind);
+        const std::vector<int> vs = variants_of(p.kind, p.n);
         if (std::find(vs.begin(), vs.end(), p.variant) == vs.end()) return false;
     }
     return ps.cblocks == 1 || ((ps.cblocks == 2 || ps.cblocks == 4 || ps.cblocks == 8) && cblocks_valid(g, ps, ps.cblocks));
@@ -889,7 +914,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         for (PassSet* ps : {&m->ps64, &m->ps32}) {
             for (int i = 0; i < ps->count; ++i)
                 if (ps->p[i].kind >= 1 && ps->p[i].kind <= 4)
-                    ps->p[i].variant = std::max(0, forced_variant(ps->p[i].kind));
+                    ps->p[i].variant = std::max(0, forced_variant(ps->p[i].kind, ps->p[i].n));
             const int blocks = forced_cblocks();
             ps->cblocks = (blocks > 0 && cblocks_valid(m->g, *ps, blocks)) ? blocks : 1;
         }
@@ -903,8 +928,8 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
         bool& done = fp64 ? m->tuned64 : m->tuned32;
         if (done) continue;
         PassSet& ps = fp64 ? m->ps64 : m->ps32;
-        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, forced_variant(4), forced_variant(1),
-                          forced_variant(2), forced_cblocks()};
+        const TuneKey key{g.ndim, g.n[0], g.n[1], g.n[2], fp64, env_pin(4), env_pin(1), env_pin(2),
+                          forced_cblocks()};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(key);
@@ -1420,6 +1445,17 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
     HIPOK(launch_zero<double>(x64, nf, st));
     HIPOK(hipMemsetAsync(ctl64, 0, sizeof(Ctl), st));
     Slot<double> h64 = make_slot<double>(m, x64, w64, y64, ctl64, part64, adjoint, at<double>(ws, L.off_chunk64));
+    // without a velocity source the FP64 right-hand side is sparse: zero
+    // velocity rows and pressure sources on few pencils (point sources, a
+    // bowl); the FP64 last-axis passes then read y only where it is non-zero
+    int yflags = 0;
+    if (!dsu) {
+        unsigned char* ypen = at<unsigned char>(ws, L.off_ypen64);
+        const int nl = g.n[g.ndim - 1];
+        HIPOK(launch_pencil_flags(y64 + (size_t)g.ndim * g.ncell, g.ncell / nl, nl, ypen, st));
+        h64.ypen = ypen;
+        yflags = 16;
+    }
     HIPOK(hipMemcpyAsync(dslot64, &h64, sizeof(h64), hipMemcpyHostToDevice, st));
 
     cbs_solve_info inf{};
@@ -1438,12 +1474,12 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
         while (true) {
             const int64_t chunk = std::min<int64_t>(check, o->max_iter - launched);
             for (int64_t k = 0; k < chunk; ++k) {
-                HIPOK(run_passes<double>(m, m->ps64, MODE_CBS, dslot64, 1, st, start));
+                HIPOK(run_passes<double>(m, m->ps64, MODE_CBS, dslot64, 1, st, start, yflags));
                 start = false;
             }
             launched += chunk;
             if (by_res) {
-                HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st));
+                HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st, true, yflags));
                 inf.residual_evals++;
                 start = true;
             }
@@ -1495,7 +1531,7 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
         // x64 = 0 so the first residual is y: evaluate it with the APPLY passes
         int64_t total = 0;
         for (int outer = 0;; ++outer) {
-            HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st));
+            HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot64, 1, st, true, yflags));
             inf.residual_evals++;
             if ((cs = read_ctl(m, ctl64, &hc, st)) != CBS_OK) return cs;
             inf.rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
@@ -1684,7 +1720,7 @@ cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]) {
         out[4 * i + 1] = have ? ps.p[i].n : 0;
         out[4 * i + 2] = have ? ps.p[i].pcols : 0;
         const int blocks = (have && ps.count == 5 && i >= 1 && i <= 3) ? ps.cblocks : 1;
-        out[4 * i + 3] = have ? ((ps.p[i].wide ? 1 : 0) | (ps.p[i].variant << 1) | (blocks << 4)) : 0;
+        out[4 * i + 3] = have ? ((ps.p[i].wide ? 1 : 0) | (ps.p[i].variant << 1) | (blocks << 5)) : 0;
     }
     return CBS_OK;
 }
@@ -2060,3 +2096,4 @@ cbs_status cbs_batch_retire(cbs_batch b, int32_t slot, void* p_out, void* u_out,
 }
 
 }  // extern "C"
+

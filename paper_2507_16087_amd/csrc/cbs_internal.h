@@ -60,6 +60,10 @@ struct Slot {
     cx<T> al12;           // al1 * al2
     int adjoint;
     int pad;
+    // sparse right-hand side (kernels built with a sparse-y flag only): the
+    // velocity rows of y are zero and its pressure row is read only on
+    // pencils whose flag is set (one byte per pencil of a field plane)
+    const unsigned char* ypen;
     Ctl* ctl;
     double* partials;     // 2 doubles per work-group of the last pass
     double* chunks;       // 2 doubles per block of the reduction

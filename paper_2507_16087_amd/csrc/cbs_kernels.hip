@@ -123,6 +123,22 @@ __global__ void k_ctl_reset(Ctl* c, int max_iter, double tol) {
     }
 }
 
+// Per-pencil flags of a sparse right-hand side: flag[k] = 1 if any of the n
+// values of pencil k (of one field plane) is non-zero.  One wave per pencil.
+__global__ void __launch_bounds__(256) k_pencil_flags(const cx<double>* __restrict__ plane, int64_t pencils, int n,
+                                                      unsigned char* __restrict__ flag) {
+    const int64_t pc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pc >= pencils) return;
+    const int lane = threadIdx.x & 63;
+    int nz = 0;
+    for (int j = lane; j < n; j += 64) {
+        const cx<double> v = plane[pc * n + j];
+        nz |= (v.re != 0.0 || v.im != 0.0);
+    }
+    nz = __any(nz);
+    if (lane == 0) flag[pc] = (unsigned char)(nz ? 1 : 0);
+}
+
 // ------------------------------------------------------- elementwise --
 template <typename T>
 __global__ void k_zero(cx<T>* p, int64_t n) {
@@ -315,11 +331,19 @@ hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, con
         GROUP_LAUNCH(5)
         GROUP_LAUNCH(6)
         GROUP_LAUNCH(7)
+        GROUP_LAUNCH(8)
+        GROUP_LAUNCH(9)
+        GROUP_LAUNCH(10)
 #undef GROUP_LAUNCH
         default: return hipErrorInvalidValue;
     }
 }
-static_assert(CBS_PLAN_GROUPS == 8, "one GROUP_LAUNCH per plan group");
+static_assert(CBS_PLAN_GROUPS == 11, "one GROUP_LAUNCH per plan group");
+
+bool plan_has_variants(int n) {
+    const int gr = plan_group(n);
+    return gr >= 0 && gr < CBS_FULL_VARIANT_GROUPS;
+}
 
 template hipError_t launch_pass<float>(int, int, const Slot<float>*, int, const Geom&, int, int, int, bool, int,
                                        hipStream_t, int, int);
@@ -340,6 +364,12 @@ template hipError_t launch_reduce<double>(bool, const Slot<double>*, int, int, h
 
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st) {
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, c, max_iter, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_pencil_flags(const cx<double>* plane, int64_t pencils, int n, unsigned char* flag,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_pencil_flags, dim3((unsigned)((pencils + 3) / 4)), dim3(256), 0, st, plane, pencils, n, flag);
     return hipGetLastError();
 }
 

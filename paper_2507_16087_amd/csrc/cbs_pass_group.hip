@@ -17,8 +17,8 @@ hipError_t launch_group(int kind, int mode, const Slot<T>* slots, int nslots, co
 #define LAUNCH_CASE(G_, N_, A, B, C, T_)                                                                         \
     if constexpr (G_ == G) {                                                                                     \
         if (n == N_)                                                                                             \
-            return launch_plan<T, Plan<N_, A, B, C, T_>>(kind, mode, slots, nslots, g, axis, pcols, variant, l0, \
-                                                         lw, st);                                                \
+            return launch_plan<T, Plan<N_, A, B, C, T_>, (G_ < CBS_FULL_VARIANT_GROUPS)>(             \
+                kind, mode, slots, nslots, g, axis, pcols, variant, l0, lw, st);                                 \
     }
     if (wide) { CBS_PLANS_WIDE(LAUNCH_CASE) }
     CBS_PLANS(LAUNCH_CASE)

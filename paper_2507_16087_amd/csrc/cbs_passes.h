@@ -416,7 +416,9 @@ enum Kind { FIRST = 0, LAST = 1, FUSED = 2 };
 //   PF (LAST / FUSED): 0 loads x, y and the medium after the inverse
 //   transform; 1 issues all three right after the w loads, so they travel
 //   while the transform runs; 2 prefetches x and the medium only.
-template <class P, int MODE, int KIND, int PF, typename T>
+//   YS: sparse right-hand side -- velocity rows of y are zero and the
+//   pressure row is read only on the pencils s.ypen flags.
+template <class P, int MODE, int KIND, int PF, bool YS, typename T>
 __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ slots, Geom g, int pcols) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -451,6 +453,16 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
     GLOBAL cx<T>* __restrict__ w = gmem(s.w) + fbase;
     GLOBAL cx<T>* __restrict__ x = gmem(s.x) + fbase;
     const GLOBAL cx<T>* __restrict__ y = gmem(s.y) + fbase;
+    // this pencil's right-hand side is all zero (sparse y: a velocity row, or
+    // a pressure pencil without a source cell)
+    bool yzero = false;
+    if constexpr (YS) yzero = f < g.ndim || !s.ypen[blockIdx.x * pcols + tid / P::TPC];
+    auto yload = [&](int n) -> cx<T> {
+        if constexpr (YS) {
+            if (yzero) return cx<T>{T(0), T(0)};
+        }
+        return ld_nt(y + pl + n);
+    };
 
     // per-pencil part of the layer rate for this field's row
     int ix[3];
@@ -499,7 +511,7 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                 if constexpr (MODE == CBS) {
                     const cx<T> dd = diag(n);
                     const cx<T> bb = {T(1) - (dd.re - are) * il, -(dd.im - aim) * il};
-                    v[b * R0 + r] = cmul(bb, xv) + ld_nt(y + pl + n);
+                    v[b * R0 + r] = cmul(bb, xv) + yload(n);
                 } else {
                     v[b * R0 + r] = xv;
                 }
@@ -521,7 +533,7 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                     const int n = out_index<P, 1>(lane, b, r);
                     xp[b * RL + r] = ld_nt(x + pl + n);
                     mp[b * RL + r] = medium(n);
-                    if constexpr (PF == 1) yp[b * RL + r] = ld_nt(y + pl + n);
+                    if constexpr (PF == 1) yp[b * RL + r] = yload(n);
                 }
         }
         fft_regs<P, 1, ROWS>(v, lds, ldp, col, lane, tw);
@@ -542,9 +554,9 @@ __global__ void __launch_bounds__(256) k_lastaxis(const Slot<T>* __restrict__ sl
                     st_nt(x + pl + n, xn);
                     acc0 += (double)norm2(dxv);
                     acc1 += (double)norm2(xv);
-                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : ld_nt(y + pl + n));
+                    if constexpr (KIND == FUSED) v[e] = cmul(bb, xn) + (PF == 1 ? yp[PF == 1 ? e : 0] : yload(n));
                 } else {
-                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : ld_nt(y + pl + n);
+                    const cx<T> yv = PF == 1 ? yp[PF == 1 ? e : 0] : yload(n);
                     const cx<T> rr = yv - rmul(il, cmul(dd, xv)) - z;
                     w[pl + n] = rr;
                     acc0 += (double)norm2(rr);
@@ -622,6 +634,33 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
             w[(uint32_t)col + (uint32_t)out_index<P, DIR>(lane, b, r) * es32] = v[b * Rl + r];
 }
 
+// ------------------------------------------------------ buffer access --
+// Raw buffer loads and stores: a resource descriptor in scalar registers
+// holds a base address and an extent in bytes, and each access takes only a
+// 32-bit byte offset in a vector register (dword 3 = the gfx9 raw-access
+// format word).  Planes of different fields share one offset each, so the
+// strided column passes keep one offset register per element instead of a
+// 64-bit address per element and field.  An offset beyond the extent reads
+// zero and drops the write.
+using bufres = __amdgpu_buffer_rsrc_t;
+template <typename T>
+__device__ __forceinline__ bufres make_res(const cx<T>* base, uint64_t bytes) {
+    const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(base), (short)0, (int)n, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> buf_load(bufres r, uint32_t off) {
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(bufres r, uint32_t off, cx<T> v) {
+    using V2 = unsigned int __attribute__((ext_vector_type(2)));
+    using V4 = unsigned int __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, 0);
+    else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, off, 0, 0);
+}
+
 // ------------------------------------- pass C: axis 0 with the propagator --
 // Forward FFT of all F fields along axis 0, per-wavevector operator, inverse
 // FFT.  MODE CBS applies (L+I)^{-1} of App. B.1 (rank-one form, conjugate
@@ -629,7 +668,9 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 // derivative block of L (negated for the adjoint).  1/prod(n) is folded in.
 //   VAR 0: one LDS tile, fields in turn; 1: one region per field, every
 //   exchange shared by all fields; 2: two regions, fields in pairs.
-template <class P, int MODE, int VAR, typename T>
+// NDIM (2 or 3) fixes the field count at compile time; the F planes of the
+// tile are read and written through buffer resources that share offsets.
+template <class P, int MODE, int VAR, int NDIM, typename T>
 __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots, Geom g, int pcols, int ldp,
                                               int64_t es, int64_t ostride, int nlast_tiles, int xg, int l0) {
     constexpr int NR = VAR == 1 ? 4 : (VAR == 2 ? 2 : 1);
@@ -638,7 +679,7 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     const Slot<T>& s = slots[blockIdx.z];
     if (MODE == CBS && s.ctl->done) return;
     constexpr int N = P::N, E = P::E;
-    const int D = g.ndim, F = D + 1;
+    constexpr int D = NDIM, F = NDIM + 1;
     const int tid = threadIdx.x;
     const int col = tid % pcols, lane = tid / pcols;
     const uint32_t es32 = (uint32_t)es;
@@ -660,23 +701,21 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     constexpr int RL = QI::r(P::S - 1);
 
     // first-stage inputs of every field of one tile, straight from HBM
-    auto load = [&](cx<T> (&v)[4][E], const GLOBAL cx<T>* __restrict__ wt) {
+    auto load = [&](cx<T> (&v)[4][E], const bufres (&res)[F]) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (f < F) {
-                const GLOBAL cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
+        for (int b = 0; b < N / (R0 * P::TPC); ++b)
 #pragma unroll
-                for (int b = 0; b < N / (R0 * P::TPC); ++b)
+            for (int r = 0; r < R0; ++r) {
+                const uint32_t off =
+                    ((uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32) * (uint32_t)sizeof(cx<T>);
 #pragma unroll
-                    for (int r = 0; r < R0; ++r)
-                        v[f][b * R0 + r] = wf[(uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32];
+                for (int f = 0; f < F; ++f) v[f][b * R0 + r] = buf_load<T>(res[f], off);
             }
-        }
     };
 
     // transforms, operator and stores of one tile whose registers are loaded;
     // the LDS regions must be free on entry
-    auto run = [&](cx<T> (&v)[4][E], int io, int il, GLOBAL cx<T>* __restrict__ wt) {
+    auto run = [&](cx<T> (&v)[4][E], int io, int il, const bufres (&res)[F]) {
         // wavevector components of this column (axes 1.., FFT order)
         T kc[2];
         cx<T> gc[2];   // k S for the column axes
@@ -787,23 +826,28 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
                     __syncthreads();
                     fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
                 }
-                GLOBAL cx<T>* __restrict__ wf = wt + (int64_t)f * g.ncell;
 #pragma unroll
                 for (int b = 0; b < N / (RL * P::TPC); ++b)
 #pragma unroll
                     for (int r = 0; r < RL; ++r)
-                        wf[(uint32_t)col + (uint32_t)out_index<P, 1>(lane, b, r) * es32] = v[f][b * RL + r];
+                        buf_store<T>(res[f], ((uint32_t)col + (uint32_t)out_index<P, 1>(lane, b, r) * es32) *
+                                                 (uint32_t)sizeof(cx<T>),
+                                     v[f][b * RL + r]);
             }
         }
     };
 
     // tile: index io along the middle axis (3-D), columns along the last
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x, xg);
-    GLOBAL cx<T>* wt = gmem(s.w) + (int64_t)(tile / nlast_tiles) * ostride + l0 + (int64_t)(tile % nlast_tiles) * pcols;
+    const int64_t toff = (int64_t)(tile / nlast_tiles) * ostride + l0 + (int64_t)(tile % nlast_tiles) * pcols;
+    bufres res[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+        res[f] = make_res<T>(s.w + (int64_t)f * g.ncell + toff, (uint64_t)(g.ncell - toff) * sizeof(cx<T>));
     cx<T> v[4][E];
     __syncthreads();   // tables staged
-    load(v, wt);
-    run(v, (int)(tile / nlast_tiles), l0 + (int)(tile % nlast_tiles) * pcols + col, wt);
+    load(v, res);
+    run(v, (int)(tile / nlast_tiles), l0 + (int)(tile % nlast_tiles) * pcols + col, res);
 }
 
 // LDS one work-group may hold on gfx950 (160 KiB per compute unit); larger
@@ -813,9 +857,12 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // Launch one pass.  kind: 0 last-axis forward with prologue, 1 last-axis
 // inverse with epilogue, 5 both fused across iterations, 2 strided forward,
 // 3 strided inverse, 4 axis-0 propagator.
-template <typename T, class P>
+// FULL: every variant is compiled for this plan; otherwise only variant 0 of
+// each pass (and the unpadded column tile, a launch-time choice).
+template <typename T, class P, bool FULL>
 static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis,
                               int pcols, int variant, int l0, int lw, hipStream_t st) {
+    if (!FULL && (variant & ~(4 | 16))) return hipErrorInvalidValue;
     const int N = P::N;
     // column tiles (strided and propagator passes) are padded by one element
     // per row unless variant bit 2 asks for the unpadded pitch
@@ -835,27 +882,55 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
         const size_t lr = std::max(tile_bytes<T>((size_t)pcols * lds_pitch<ROWS>(N, 0)), (size_t)(64 * sizeof(double))) +
                           (size_t)N * (sizeof(cx<T>) + sizeof(T));
         if (lr > kMaxLdsBytes) return hipErrorInvalidConfiguration;
-        // last-axis inverse passes: the variant is the prefetch
-        const int pf = variant;
-#define LA_LAUNCH(M, K, PF_) hipLaunchKernelGGL((k_lastaxis<P, M, K, PF_, T>), grid, blk, lr, st, slots, g, pcols)
+        // last-axis passes: variant bits 0-1 = prefetch of the inverse pass,
+        // bit 4 = sparse right-hand side (kernels for it exist in FP64 for the
+        // full-variant plans; elsewhere the dense y, always complete, is read)
+        const bool ys = (variant & 16) && sizeof(T) == 8 && FULL;
+        const int pf = variant & 3;
+#define LA_LAUNCH(M, K, PF_, YS_) \
+    hipLaunchKernelGGL((k_lastaxis<P, M, K, PF_, YS_, T>), grid, blk, lr, st, slots, g, pcols)
+#define LA_YS(M, K, PF_)                                      \
+    do {                                                      \
+        if constexpr (sizeof(T) == 8 && FULL) {               \
+            if (ys) LA_LAUNCH(M, K, PF_, true);               \
+            else LA_LAUNCH(M, K, PF_, false);                 \
+        } else {                                              \
+            LA_LAUNCH(M, K, PF_, false);                      \
+        }                                                     \
+    } while (0)
+        // residual (APPLY) passes run in FP64 only
+        if (mode != CBS && sizeof(T) != 8) return hipErrorInvalidValue;
         if (kind == 0) {
-            if (mode == CBS) LA_LAUNCH(CBS, FIRST, 0);
-            else LA_LAUNCH(APPLY, FIRST, 0);
+            if (mode == CBS) LA_YS(CBS, FIRST, 0);
+            else if constexpr (sizeof(T) == 8) LA_LAUNCH(APPLY, FIRST, 0, false);
         } else if (kind == 1) {
             if (mode == CBS) {
-                if (pf == 1) LA_LAUNCH(CBS, LAST, 1);
-                else if (pf == 2) LA_LAUNCH(CBS, LAST, 2);
-                else LA_LAUNCH(CBS, LAST, 0);
-            } else {
-                if (pf == 1) LA_LAUNCH(APPLY, LAST, 1);
-                else if (pf == 2) LA_LAUNCH(APPLY, LAST, 2);
-                else LA_LAUNCH(APPLY, LAST, 0);
+                if constexpr (FULL) {
+                    if (pf == 1) LA_LAUNCH(CBS, LAST, 1, false);
+                    else if (pf == 2) LA_LAUNCH(CBS, LAST, 2, false);
+                    else LA_LAUNCH(CBS, LAST, 0, false);
+                } else {
+                    LA_LAUNCH(CBS, LAST, 0, false);
+                }
+            } else if constexpr (sizeof(T) == 8) {
+                if constexpr (FULL) {
+                    if (pf == 1) LA_YS(APPLY, LAST, 1);
+                    else if (pf == 2) LA_YS(APPLY, LAST, 2);
+                    else LA_YS(APPLY, LAST, 0);
+                } else {
+                    LA_LAUNCH(APPLY, LAST, 0, false);
+                }
             }
         } else {
-            if (pf == 1) LA_LAUNCH(CBS, FUSED, 1);
-            else if (pf == 2) LA_LAUNCH(CBS, FUSED, 2);
-            else LA_LAUNCH(CBS, FUSED, 0);
+            if constexpr (FULL) {
+                if (pf == 1) LA_YS(CBS, FUSED, 1);
+                else if (pf == 2) LA_YS(CBS, FUSED, 2);
+                else LA_YS(CBS, FUSED, 0);
+            } else {
+                LA_LAUNCH(CBS, FUSED, 0, false);
+            }
         }
+#undef LA_YS
 #undef LA_LAUNCH
     } else {
         // strided along `axis`; columns run along the last axis in groups of pcols
@@ -886,16 +961,31 @@ static hipError_t launch_plan(int kind, int mode, const Slot<T>* slots, int nslo
             const size_t lp = lds + (size_t)(nr - 1) * tile_bytes<T>((size_t)N * ldp);
             if (lp > kMaxLdsBytes) return hipErrorInvalidConfiguration;
 #define PROP_LAUNCH(M, V)                                                                                     \
-    hipLaunchKernelGGL((k_prop<P, M, V, T>), grid, block, lp, st, slots, g, pcols, ldp, es, ostride, nlast_tiles, \
-                       xg, l0)
+    do {                                                                                                      \
+        if (g.ndim == 3)                                                                                      \
+            hipLaunchKernelGGL((k_prop<P, M, V, 3, T>), grid, block, lp, st, slots, g, pcols, ldp, es, ostride, \
+                               nlast_tiles, xg, l0);                                                          \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_prop<P, M, V, 2, T>), grid, block, lp, st, slots, g, pcols, ldp, es, ostride, \
+                               nlast_tiles, xg, l0);                                                          \
+    } while (0)
+            if (mode != CBS && sizeof(T) != 8) return hipErrorInvalidValue;
             if (mode == CBS) {
-                if (variant == 1) PROP_LAUNCH(CBS, 1);
-                else if (variant == 2) PROP_LAUNCH(CBS, 2);
-                else PROP_LAUNCH(CBS, 0);
-            } else {
-                if (variant == 1) PROP_LAUNCH(APPLY, 1);
-                else if (variant == 2) PROP_LAUNCH(APPLY, 2);
-                else PROP_LAUNCH(APPLY, 0);
+                if constexpr (FULL) {
+                    if (variant == 1) PROP_LAUNCH(CBS, 1);
+                    else if (variant == 2) PROP_LAUNCH(CBS, 2);
+                    else PROP_LAUNCH(CBS, 0);
+                } else {
+                    PROP_LAUNCH(CBS, 0);
+                }
+            } else if constexpr (sizeof(T) == 8) {
+                if constexpr (FULL) {
+                    if (variant == 1) PROP_LAUNCH(APPLY, 1);
+                    else if (variant == 2) PROP_LAUNCH(APPLY, 2);
+                    else PROP_LAUNCH(APPLY, 0);
+                } else {
+                    PROP_LAUNCH(APPLY, 0);
+                }
             }
 #undef PROP_LAUNCH
         } else {

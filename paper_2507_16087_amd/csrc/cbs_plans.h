@@ -34,13 +34,13 @@
     X(6, 108, 6, 6, 3, 18)           \
     X(6, 144, 12, 12, 1, 12)         \
     X(6, 162, 2, 9, 9, 9)            \
-    X(6, 216, 12, 3, 6, 18)          \
-    X(6, 243, 3, 9, 9, 27)           \
-    X(7, 288, 4, 6, 12, 24)          \
-    X(7, 324, 6, 6, 9, 18)           \
-    X(7, 384, 8, 8, 6, 16)           \
-    X(7, 432, 12, 6, 6, 36)          \
-    X(7, 486, 6, 9, 9, 27)
+    X(7, 216, 12, 3, 6, 18)          \
+    X(7, 243, 3, 9, 9, 27)           \
+    X(8, 288, 4, 6, 12, 24)          \
+    X(8, 324, 6, 6, 9, 18)           \
+    X(9, 384, 8, 8, 6, 16)           \
+    X(10, 432, 12, 6, 6, 36)         \
+    X(10, 486, 6, 9, 9, 27)
 
 // Alternative plans with fewer elements per thread (for register-heavy
 // passes), chosen per pass by the tuner.
@@ -49,4 +49,10 @@
     X(2, 128, 4, 4, 8, 16)           \
     X(3, 256, 4, 8, 8, 32)
 
-#define CBS_PLAN_GROUPS 8
+#define CBS_PLAN_GROUPS 11
+
+// Groups below this one compile every pass variant the tuner chooses from
+// (LDS layouts of the propagator pass, prefetch of the last-axis inverse
+// pass); the lengths of the later groups, off the benchmarked shapes, compile
+// the baseline variant of each pass only.
+#define CBS_FULL_VARIANT_GROUPS 5

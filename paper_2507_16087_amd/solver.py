@@ -151,8 +151,8 @@ class Medium:
         cfg = (C.c_int32 * 20)()
         L.check(L.lib().cbs_pass_config(self._h, PREC[prec], cfg), "cbs_pass_config")
         return [dict(kind=cfg[4 * i], n=cfg[4 * i + 1], cols=cfg[4 * i + 2],
-                     wide=cfg[4 * i + 3] & 1, variant=(cfg[4 * i + 3] >> 1) & 7,
-                     blocks=cfg[4 * i + 3] >> 4)
+                     wide=cfg[4 * i + 3] & 1, variant=(cfg[4 * i + 3] >> 1) & 15,
+                     blocks=cfg[4 * i + 3] >> 5)
                 for i in range(5) if cfg[4 * i] >= 0]
 
     def workspace_bytes(self, prec="fp64", batch=1) -> int:
