@@ -197,6 +197,26 @@ cbs_status cbs_residual(cbs_medium m, const void *s_p, const void *s_u, const vo
                         double *rel_residual, void *r_p, void *r_u, void *workspace,
                         size_t ws_bytes, void *hip_stream);
 
+/* Bytes of the device array cbs_residual_noalloc works in (per GPU). */
+#define CBS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* cbs_residual without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Arguments, outputs
+ * and errors as cbs_residual.  Its kernels work in a file-scope device array
+ * of CBS_NOALLOC_SCRATCH_BYTES that each GPU holds from the library's load
+ * until the process ends; grids whose residual workspace
+ * (cbs_workspace_bytes(m, CBS_FP64, 1)) exceeds it return CBS_E_NOMEM before
+ * any device work (about 64^3 cells in 3-D).  It does not tune: it runs the
+ * pass plans the medium holds (tuned by an earlier solve or residual call,
+ * else the default plans).  Every call on one GPU shares that GPU's array,
+ * which keeps the last call's contents; calls that overlap on one GPU (other
+ * threads, other streams) race and must be serialised by the caller. */
+cbs_status cbs_residual_noalloc(cbs_medium m, const void *s_p, const void *s_u, const void *p,
+                                const void *u, int32_t adjoint, int32_t rhs_kind,
+                                int32_t ptr_kind, double *rel_residual, void *r_p, void *r_u,
+                                void *hip_stream);
+
 /* Misfit gradient with respect to c, rho and alpha (adjoint-state method on
  * the adjoint operator of Sec. 2.3).  Given the physical source (s_p, s_u),
  * the forward solution (p, u) of A xi = s_hat and the adjoint solution

@@ -29,6 +29,7 @@ CBS_RHS_PHYSICAL = 0
 CBS_RHS_EQUATION = 1
 CBS_STOP_UPDATE = 0
 CBS_STOP_RESIDUAL = 1
+CBS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every entry point declared in include/cbs.h
 EXPORTS = [
@@ -36,7 +37,7 @@ EXPORTS = [
     "cbs_workspace_bytes", "cbs_solve", "cbs_solve_adjoint", "cbs_residual", "cbs_gradient",
     "cbs_pass_config", "cbs_pass_timing", "cbs_pass_timing_slots", "cbs_pass_timing_read",
     "cbs_batch_workspace_bytes", "cbs_batch_create", "cbs_batch_destroy", "cbs_batch_submit",
-    "cbs_batch_step", "cbs_batch_retire",
+    "cbs_batch_step", "cbs_batch_retire", "cbs_residual_noalloc",
 ]
 
 
@@ -84,6 +85,7 @@ def lib() -> C.CDLL:
     L.cbs_solve.argtypes = solve_args
     L.cbs_solve_adjoint.argtypes = solve_args
     L.cbs_residual.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, dp, vp, vp, vp, C.c_size_t, vp]
+    L.cbs_residual_noalloc.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, dp, vp, vp, vp]
     L.cbs_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
     L.cbs_pass_config.argtypes = [vp, i32, C.POINTER(C.c_int32)]
     L.cbs_pass_timing.argtypes = [vp, i32]

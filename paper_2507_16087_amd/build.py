@@ -23,7 +23,7 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcbs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cbs_kernels.hip", "cbs_host.cpp"]
+SOURCES = ["cbs_kernels.hip", "cbs_host.cpp", "cbs_noalloc.hip"]
 # the FFT pass kernels, one object per plan group (see csrc/cbs_plans.h)
 PLAN_GROUPS = 11
 GROUP_SRC = "cbs_pass_group.hip"

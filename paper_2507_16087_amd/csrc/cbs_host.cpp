@@ -32,6 +32,7 @@ hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, con
 template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st);
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st);
+hipError_t launch_ctl_clear(Ctl* c, hipStream_t st);
 hipError_t launch_pencil_flags(const cx<double>* plane, int64_t pencils, int n, unsigned char* flag,
                                hipStream_t st);
 template <typename T>
@@ -1584,33 +1585,31 @@ cbs_status solve_impl(cbs_medium m, const void* s_p, const void* s_u, const cbs_
 
 }  // namespace
 
-extern "C" {
-
-cbs_status cbs_solve(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts, void* p_out,
-                     void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info, void* hip_stream) {
-    return guarded([&] { return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 0); });
-}
-
-cbs_status cbs_solve_adjoint(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts,
-                             void* p_out, void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info,
-                             void* hip_stream) {
-    return guarded([&] { return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 1); });
-}
-
-cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,
-                        int32_t adjoint, int32_t rhs_kind, int32_t ptr_kind, double* rel_residual, void* r_p,
-                        void* r_u, void* workspace, size_t ws_bytes, void* hip_stream) {
+namespace cbs {
+// Body of cbs_residual.  no_alloc: the allocation-free entry point's path --
+// no tuning (the pass set the medium holds is used as it stands: tuned by an
+// earlier call, or the default plans) and the control block cleared by a
+// kernel rather than a memset; nothing here allocates.
+cbs_status residual_impl(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,
+                         int32_t adjoint, int32_t rhs_kind, int32_t ptr_kind, double* rel_residual, void* r_p,
+                         void* r_u, void* workspace, size_t ws_bytes, hipStream_t st, bool no_alloc) {
     if (!m || !s_p || !p || !workspace) return CBS_E_INVALID;
     if (ptr_kind != CBS_PTR_HOST && ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
     if (rhs_kind != CBS_RHS_PHYSICAL && rhs_kind != CBS_RHS_EQUATION) return CBS_E_INVALID;
     const Layout L = layout_for(m, CBS_FP64);
     if (ws_bytes < L.total) return CBS_E_NOMEM;
-    hipStream_t st = (hipStream_t)hip_stream;
     const Geom& g = m->g;
     const int64_t N = g.ncell;
     const int D = g.ndim;
-    cbs_status ts = guarded([&] { return ensure_tuned(m, CBS_FP64, workspace, st); });
-    if (ts != CBS_OK) return ts;
+    PassSet ps;
+    if (no_alloc) {
+        std::lock_guard<std::mutex> lk(m->tune_mu);
+        ps = m->ps64;
+    } else {
+        cbs_status ts = guarded([&] { return ensure_tuned(m, CBS_FP64, workspace, st); });
+        if (ts != CBS_OK) return ts;
+        ps = m->ps64;
+    }
     Slot<double>* dslot = at<Slot<double>>(workspace, L.off_slot64);
     Ctl* ctl = at<Ctl>(workspace, L.off_ctl64);
     cx<double>* x = at<cx<double>>(workspace, L.off_x64);
@@ -1627,10 +1626,11 @@ cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const vo
     cs = stage_sources(m, p, u, ptr_kind, w, &dp, &du, st);
     if (cs != CBS_OK) return cs;
     HIPOK(launch_scale_in(g, dp, du, std::sqrt(m->lam1), std::sqrt(m->lam2), x, st));
-    HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+    if (no_alloc) HIPOK(launch_ctl_clear(ctl, st));
+    else HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
     Slot<double> h = make_slot<double>(m, x, w, y, ctl, part, adjoint ? 1 : 0, at<double>(workspace, L.off_chunk64));
     HIPOK(hipMemcpyAsync(dslot, &h, sizeof(h), hipMemcpyHostToDevice, st));
-    HIPOK(run_passes<double>(m, m->ps64, MODE_APPLY, dslot, 1, st));
+    HIPOK(run_passes<double>(m, ps, MODE_APPLY, dslot, 1, st));
     Ctl hc{};
     if ((cs = read_ctl(m, ctl, &hc, st)) != CBS_OK) return cs;
     if (rel_residual) *rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
@@ -1648,6 +1648,30 @@ cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const vo
         HIPOK(hipStreamSynchronize(st));
     }
     return CBS_OK;
+}
+
+// Bytes of device memory cbs_residual's kernels use beyond inputs and outputs.
+size_t residual_workspace_bytes(cbs_medium m) { return layout_for(m, CBS_FP64).total; }
+}  // namespace cbs
+
+extern "C" {
+
+cbs_status cbs_solve(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts, void* p_out,
+                     void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info, void* hip_stream) {
+    return guarded([&] { return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 0); });
+}
+
+cbs_status cbs_solve_adjoint(cbs_medium m, const void* s_p, const void* s_u, const cbs_solve_opts* opts,
+                             void* p_out, void* u_out, void* workspace, size_t ws_bytes, cbs_solve_info* info,
+                             void* hip_stream) {
+    return guarded([&] { return solve_impl(m, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream, 1); });
+}
+
+cbs_status cbs_residual(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,
+                        int32_t adjoint, int32_t rhs_kind, int32_t ptr_kind, double* rel_residual, void* r_p,
+                        void* r_u, void* workspace, size_t ws_bytes, void* hip_stream) {
+    return residual_impl(m, s_p, s_u, p, u, adjoint, rhs_kind, ptr_kind, rel_residual, r_p, r_u, workspace,
+                         ws_bytes, (hipStream_t)hip_stream, false);
 }
 
 cbs_status cbs_gradient(cbs_medium m, const void* s_p, const void* s_u, const void* p, const void* u,

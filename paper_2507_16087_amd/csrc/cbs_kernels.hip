@@ -123,6 +123,12 @@ __global__ void k_ctl_reset(Ctl* c, int max_iter, double tol) {
     }
 }
 
+// every field of a control block to zero (a kernel, so that no memset node
+// lands in a caller's captured graph)
+__global__ void k_ctl_clear(Ctl* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = Ctl{};
+}
+
 // Per-pencil flags of a sparse right-hand side: flag[k] = 1 if any of the n
 // values of pencil k (of one field plane) is non-zero.  One wave per pencil.
 __global__ void __launch_bounds__(256) k_pencil_flags(const cx<double>* __restrict__ plane, int64_t pencils, int n,
@@ -364,6 +370,11 @@ template hipError_t launch_reduce<double>(bool, const Slot<double>*, int, int, h
 
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st) {
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, c, max_iter, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_clear(Ctl* c, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctl_clear, dim3(1), dim3(64), 0, st, c);
     return hipGetLastError();
 }
 
