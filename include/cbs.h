@@ -228,6 +228,27 @@ cbs_status cbs_gradient(cbs_medium m, const void *s_p, const void *s_u, const vo
                         const void *u, const void *lp, const void *lu, int32_t ptr_kind,
                         double *g_c, double *g_rho, double *g_alpha, void *hip_stream);
 
+/* Slab decomposition of one solve (the Discussion names domain decomposition
+ * as the way to spread a solve over several GPUs), run on the current device
+ * the way `parts` devices would run it: part g owns the axis-0 planes
+ * [g s, (g+1) s) (s = n0 / parts) of the state, the right-hand side, the work
+ * array and the medium, and runs the last-axis and axis-1 passes on them;
+ * an exchange (the all-to-all of a multi-device run, here a device copy)
+ * regroups the work array into axis-1 row groups [h t, (h+1) t)
+ * (t = n1 / parts) for the axis-0 pass with the propagator, whose wavenumber
+ * tables are offset to the group's rows, and a second exchange regroups it
+ * back; one reduction folds every part's norm partial sums.  Every pass is
+ * launched per part at the part's own shape.  Same arithmetic per pencil as
+ * cbs_solve, so the same iterates; only the order in which the norm partial
+ * sums are added differs.  ndim must be 3 and parts (1..64) must divide n0
+ * and n1, else CBS_E_UNSUPPORTED.  Forward problem only.  Other
+ * arguments, outputs and errors as cbs_solve; workspace: at least
+ * cbs_split_workspace_bytes(m, opts->prec, parts) bytes. */
+cbs_status cbs_split_workspace_bytes(cbs_medium m, int32_t prec, int32_t parts, size_t *bytes);
+cbs_status cbs_solve_split(cbs_medium m, int32_t parts, const void *s_p, const void *s_u,
+                           const cbs_solve_opts *opts, void *p_out, void *u_out, void *workspace,
+                           size_t ws_bytes, cbs_solve_info *info, void *hip_stream);
+
 /* Per-pass GPU time accounting for measurement: with enable = 1 (which also
  * clears the totals) every pass launch of this medium's solves is bracketed
  * by HIP events on the solve's stream and folded into running totals at each

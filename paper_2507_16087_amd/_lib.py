@@ -37,7 +37,8 @@ EXPORTS = [
     "cbs_workspace_bytes", "cbs_solve", "cbs_solve_adjoint", "cbs_residual", "cbs_gradient",
     "cbs_pass_config", "cbs_pass_timing", "cbs_pass_timing_slots", "cbs_pass_timing_read",
     "cbs_batch_workspace_bytes", "cbs_batch_create", "cbs_batch_destroy", "cbs_batch_submit",
-    "cbs_batch_step", "cbs_batch_retire", "cbs_residual_noalloc",
+    "cbs_batch_step", "cbs_batch_retire", "cbs_residual_noalloc", "cbs_split_workspace_bytes",
+    "cbs_solve_split",
 ]
 
 
@@ -85,6 +86,9 @@ def lib() -> C.CDLL:
     L.cbs_solve.argtypes = solve_args
     L.cbs_solve_adjoint.argtypes = solve_args
     L.cbs_residual.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, dp, vp, vp, vp, C.c_size_t, vp]
+    L.cbs_split_workspace_bytes.argtypes = [vp, i32, i32, C.POINTER(C.c_size_t)]
+    L.cbs_solve_split.argtypes = [vp, i32, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, C.c_size_t,
+                                  C.POINTER(SolveInfo), vp]
     L.cbs_residual_noalloc.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, dp, vp, vp, vp]
     L.cbs_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
     L.cbs_pass_config.argtypes = [vp, i32, C.POINTER(C.c_int32)]

@@ -2121,3 +2121,351 @@ cbs_status cbs_batch_retire(cbs_batch b, int32_t slot, void* p_out, void* u_out,
 
 }  // extern "C"
 
+// ------------------------------------------------------------ slab split --
+// One solve split along axis 0 into G parts, run the way G devices would run
+// it, on the current device: part g owns planes [g s, (g+1) s) of x, y, the
+// work array and the medium (s = n0 / G) and runs the last-axis and axis-1
+// passes on them; an all-to-all exchange turns the parts into axis-1 pencil
+// groups (part h owns rows [h t, (h+1) t), t = n1 / G, for every axis-0
+// index) for the axis-0 pass with the propagator, whose wavenumber tables are
+// offset to part h's rows, and a second exchange turns them back; the norm
+// partial sums of all parts are folded by one reduction (the all-reduce).
+// Every pass is launched per part, at the part's own shape.
+namespace cbs {
+template <typename E>
+hipError_t launch_relayout(const E* src, int src_lay, E* dst, int dst_lay, int F, const int* n, int G,
+                           hipStream_t st);
+}
+
+namespace {
+
+enum { LAY_WHOLE = 0, LAY_SLAB = 1, LAY_PENCIL = 2 };
+
+struct SplitLayout {
+    size_t off_ctl64, off_slots64, off_part64, off_chunk64, off_x64, off_w64, off_y64, off_p64, off_rb64;
+    size_t off_ctl32, off_slots32, off_part32, off_chunk32, off_d32, off_w32, off_y32, off_p32, off_rb32;
+    size_t total;
+};
+
+SplitLayout split_layout_for(const Geom& g, int prec, int G) {
+    SplitLayout L{};
+    const size_t F = (size_t)g.ndim + 1, N = (size_t)g.ncell, D = (size_t)g.ndim;
+    const size_t maxparts = F * (N / (size_t)g.n[g.ndim - 1]);   // one pair per pencil at most, all parts
+    const size_t maxchunks = (maxparts + kReduceChunk - 1) / kReduceChunk;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.off_ctl64 = take(sizeof(Ctl));
+    L.off_slots64 = take(sizeof(Slot<double>) * (2 * (size_t)G + 1));
+    L.off_part64 = take(sizeof(double) * 2 * maxparts);
+    L.off_chunk64 = take(sizeof(double) * 2 * maxchunks);
+    L.off_x64 = take(F * N * sizeof(cx<double>));
+    L.off_w64 = take(F * N * sizeof(cx<double>));
+    L.off_y64 = take(F * N * sizeof(cx<double>));
+    L.off_p64 = take(F * N * sizeof(cx<double>));
+    L.off_rb64 = take(D * N * sizeof(double));
+    if (prec == CBS_FP32_REFINED) {
+        L.off_ctl32 = take(sizeof(Ctl));
+        L.off_slots32 = take(sizeof(Slot<float>) * (2 * (size_t)G + 1));
+        L.off_part32 = take(sizeof(double) * 2 * maxparts);
+        L.off_chunk32 = take(sizeof(double) * 2 * maxchunks);
+        L.off_d32 = take(F * N * sizeof(cx<float>));
+        L.off_w32 = take(F * N * sizeof(cx<float>));
+        L.off_y32 = take(F * N * sizeof(cx<float>));
+        L.off_p32 = take(F * N * sizeof(cx<float>));
+        L.off_rb32 = take(D * N * sizeof(float));
+    }
+    // the tuner runs on the same workspace with the unsplit layout
+    L.total = std::max(o, layout_for(g, prec).total);
+    return L;
+}
+
+cbs_status split_check(const cbs_medium_s* m, int G) {
+    if (!m || G < 1 || G > 64) return CBS_E_INVALID;
+    if (m->g.ndim != 3) return CBS_E_UNSUPPORTED;
+    if (m->g.n[0] % G || m->g.n[1] % G) return CBS_E_UNSUPPORTED;
+    return CBS_OK;
+}
+
+// The passes of one part: the tuned plans of the whole grid where their
+// tile widths fit the part's shapes, the default plans otherwise.
+PassSet split_passes(const cbs_medium_s* m, const PassSet& tuned, const Geom& gs, bool fp64) {
+    PassSet ps = tuned;
+    ps.cblocks = 1;
+    // only the last-axis passes see the slab's own pencil count (its axis 0,
+    // n0 / parts planes, is never transformed, and may have no plan)
+    const int64_t pencils = gs.ncell / gs.n[2];
+    for (int i : {0, ps.count - 1})
+        if (ps.p[i].pcols < 1 || pencils % ps.p[i].pcols) ps.p[i] = contig_pass(gs, ps.p[i].kind, fp64);
+    const Pass& lp = ps.p[ps.count - 1];
+    ps.nparts = (int)((gs.ndim + 1) * (gs.ncell / ((int64_t)lp.n * lp.pcols)));
+    (void)m;
+    return ps;
+}
+
+template <typename T>
+struct SplitRun {
+    Geom gs, gp;               // one part's slab and pencil-group shapes
+    int G;
+    int n[3];
+    PassSet ps;
+    const Slot<T>* slots;      // device: G slab slots, G pencil slots, the reduction slot
+    cx<T>* w_slab;
+    cx<T>* w_pen;
+};
+
+// Slot descriptors of every part (host side), uploaded by the caller.
+template <typename T>
+void split_slots(const cbs_medium_s* m, const SplitRun<T>& r, cx<T>* x, cx<T>* y, const T* rb, const cx<T>* q,
+                 T* const* gc, T* const* gsp, T* const* kv, cx<T>* const* sh, Ctl* ctl, double* part,
+                 double* chunks, Slot<T>* out) {
+    const int G = r.G;
+    const int64_t sc = r.gs.ncell, pc = r.gp.ncell;
+    const int F = 4, D = 3;
+    const int s = r.n[0] / G, t = r.n[1] / G;
+    for (int g = 0; g < G; ++g) {
+        Slot<T> sl = make_slot<T>(m, x + (int64_t)g * F * sc, r.w_slab + (int64_t)g * F * sc,
+                                  y + (int64_t)g * F * sc, ctl, part + (int64_t)g * r.ps.nparts * 2, 0, chunks);
+        sl.rhobar = rb + (int64_t)g * D * sc;
+        sl.q = q + (int64_t)g * sc;
+        sl.gc[0] = gc[0] + (int64_t)g * s;
+        sl.gs[0] = gsp[0] + (int64_t)g * s;
+        out[g] = sl;
+        Slot<T> pn = make_slot<T>(m, nullptr, r.w_pen + (int64_t)g * F * pc, nullptr, ctl, nullptr, 0, chunks);
+        pn.kv[1] = kv[1] + (int64_t)g * t;
+        pn.sh[1] = sh[1] + (int64_t)g * t;
+        out[G + g] = pn;
+    }
+    out[2 * G] = make_slot<T>(m, nullptr, nullptr, nullptr, ctl, part, 0, chunks);
+}
+
+// One CBS iteration (or one residual evaluation) of the split solve.
+template <typename T>
+hipError_t split_iteration(const SplitRun<T>& r, int mode, bool start, hipStream_t st) {
+    const Pass* P = r.ps.p;
+    const Slot<T>* slab = r.slots;
+    const Slot<T>* pen = r.slots + r.G;
+    hipError_t e;
+    auto pass = [&](int kind, const Slot<T>* sl, const Geom& g, const Pass& p) {
+        return launch_pass<T>(kind, mode, sl, 1, g, p.axis, p.n, p.pcols, p.wide, p.variant, st, 0, 0);
+    };
+    for (int g = 0; g < r.G; ++g) {
+        if ((mode == MODE_APPLY || start) && (e = pass(0, slab + g, r.gs, P[0])) != hipSuccess) return e;
+        if ((e = pass(2, slab + g, r.gs, P[1])) != hipSuccess) return e;
+    }
+    if ((e = launch_relayout<cx<T>>(r.w_slab, LAY_SLAB, r.w_pen, LAY_PENCIL, 4, r.n, r.G, st)) != hipSuccess)
+        return e;
+    for (int h = 0; h < r.G; ++h)
+        if ((e = pass(4, pen + h, r.gp, P[2])) != hipSuccess) return e;
+    if ((e = launch_relayout<cx<T>>(r.w_pen, LAY_PENCIL, r.w_slab, LAY_SLAB, 4, r.n, r.G, st)) != hipSuccess)
+        return e;
+    for (int g = 0; g < r.G; ++g) {
+        if ((e = pass(3, slab + g, r.gs, P[3])) != hipSuccess) return e;
+        if ((e = pass(mode == MODE_CBS ? 5 : 1, slab + g, r.gs, P[4])) != hipSuccess) return e;
+    }
+    return launch_reduce<T>(mode == MODE_CBS, r.slots + 2 * r.G, r.G * r.ps.nparts, 1, st);
+}
+
+template <typename T>
+SplitRun<T> split_run(const cbs_medium_s* m, const PassSet& tuned, int G, cx<T>* w_slab, cx<T>* w_pen,
+                      const Slot<T>* dslots) {
+    SplitRun<T> r{};
+    r.G = G;
+    for (int d = 0; d < 3; ++d) r.n[d] = m->g.n[d];
+    r.gs = Geom{3, {r.n[0] / G, r.n[1], r.n[2]}, (int64_t)(r.n[0] / G) * r.n[1] * r.n[2]};
+    r.gp = Geom{3, {r.n[0], r.n[1] / G, r.n[2]}, (int64_t)r.n[0] * (r.n[1] / G) * r.n[2]};
+    r.ps = split_passes(m, tuned, r.gs, sizeof(T) == 8);
+    r.slots = dslots;
+    r.w_slab = w_slab;
+    r.w_pen = w_pen;
+    return r;
+}
+
+cbs_status solve_split_impl(cbs_medium m, int G, const void* s_p, const void* s_u, const cbs_solve_opts* o,
+                            void* p_out, void* u_out, void* ws, size_t wsb, cbs_solve_info* info,
+                            void* hip_stream) {
+    const double t0 = now_s();
+    cbs_status cs = split_check(m, G);
+    if (cs != CBS_OK) return cs;
+    if (!s_p || !o || !p_out || !ws) return CBS_E_INVALID;
+    if (o->prec != CBS_FP64 && o->prec != CBS_FP32_REFINED) return CBS_E_INVALID;
+    if (o->ptr_kind != CBS_PTR_HOST && o->ptr_kind != CBS_PTR_DEVICE) return CBS_E_INVALID;
+    if (o->rhs_kind != CBS_RHS_PHYSICAL && o->rhs_kind != CBS_RHS_EQUATION) return CBS_E_INVALID;
+    if (o->stop_rule != CBS_STOP_UPDATE && o->stop_rule != CBS_STOP_RESIDUAL) return CBS_E_INVALID;
+    if (!(o->tol >= 0) || o->max_iter < 1 || o->max_iter > 0x7fffffff) return CBS_E_INVALID;
+    const SplitLayout L = split_layout_for(m->g, o->prec, G);
+    if (wsb < L.total) return CBS_E_NOMEM;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geom& g = m->g;
+    const int64_t N = g.ncell, nf = 4 * N;
+    const int check = o->check_every > 0 ? o->check_every : 32;
+    if ((cs = ensure_tuned(m, o->prec, ws, st)) != CBS_OK) return cs;
+    const int n[3] = {g.n[0], g.n[1], g.n[2]};
+
+    Ctl* ctl64 = at<Ctl>(ws, L.off_ctl64);
+    Slot<double>* dslots64 = at<Slot<double>>(ws, L.off_slots64);
+    cx<double>* x64 = at<cx<double>>(ws, L.off_x64);
+    cx<double>* w64 = at<cx<double>>(ws, L.off_w64);
+    cx<double>* y64 = at<cx<double>>(ws, L.off_y64);
+    cx<double>* p64 = at<cx<double>>(ws, L.off_p64);
+    double* rb64 = at<double>(ws, L.off_rb64);
+    const SplitRun<double> r64 = split_run<double>(m, m->ps64, G, w64, p64, dslots64);
+
+    // right-hand side in the whole-grid layout (staged through the pencil
+    // array), then split into parts; the medium's staggered densities too
+    const cx<double>*dsp = nullptr, *dsu = nullptr;
+    if ((cs = stage_sources(m, s_p, s_u, o->ptr_kind, w64, &dsp, &dsu, st)) != CBS_OK) return cs;
+    HIPOK(launch_rhs(g, dsp, dsu, m->rhobar64, m->q64, o->rhs_kind == CBS_RHS_PHYSICAL, 1.0 / std::sqrt(m->lam1),
+                     1.0 / std::sqrt(m->lam2), p64, nullptr, st));
+    HIPOK(launch_relayout<cx<double>>(p64, LAY_WHOLE, y64, LAY_SLAB, 4, n, G, st));
+    HIPOK(launch_relayout<double>(m->rhobar64, LAY_WHOLE, rb64, LAY_SLAB, 3, n, G, st));
+    HIPOK(launch_zero<double>(x64, nf, st));
+    HIPOK(launch_ctl_clear(ctl64, st));
+    {
+        std::vector<Slot<double>> hs(2 * G + 1);
+        split_slots<double>(m, r64, x64, y64, rb64, m->q64, m->gc64, m->gs64, m->kv64, m->sh64, ctl64,
+                            at<double>(ws, L.off_part64), at<double>(ws, L.off_chunk64), hs.data());
+        HIPOK(hipMemcpyAsync(dslots64, hs.data(), sizeof(Slot<double>) * hs.size(), hipMemcpyHostToDevice, st));
+        HIPOK(hipStreamSynchronize(st));
+    }
+
+    cbs_solve_info inf{};
+    inf.rel_residual = -1.0;
+    Ctl hc{};
+    int status = CBS_NOT_CONVERGED;
+    if (o->prec == CBS_FP64) {
+        const bool by_res = o->stop_rule == CBS_STOP_RESIDUAL;
+        HIPOK(launch_ctl_reset(ctl64, (int)o->max_iter, by_res ? -1.0 : o->tol, st));
+        int64_t launched = 0;
+        bool start = true;
+        while (true) {
+            const int64_t chunk = std::min<int64_t>(check, o->max_iter - launched);
+            for (int64_t k = 0; k < chunk; ++k) {
+                HIPOK(split_iteration<double>(r64, MODE_CBS, start, st));
+                start = false;
+            }
+            launched += chunk;
+            if (by_res) {
+                HIPOK(split_iteration<double>(r64, MODE_APPLY, true, st));
+                inf.residual_evals++;
+                start = true;
+            }
+            if ((cs = read_ctl(m, ctl64, &hc, st)) != CBS_OK) return cs;
+            inf.iterations = hc.iter;
+            inf.rel_update = hc.rel_update;
+            if (by_res) {
+                inf.rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
+                if (!std::isfinite(inf.rel_residual)) {
+                    status = CBS_E_DIVERGED;
+                    break;
+                }
+                if (inf.rel_residual <= o->tol) {
+                    status = CBS_OK;
+                    break;
+                }
+            }
+            if (hc.done == CONVERGED) {
+                status = CBS_OK;
+                break;
+            }
+            if (hc.done == DIVERGED) {
+                status = CBS_E_DIVERGED;
+                break;
+            }
+            if (hc.done == CAPPED || launched >= o->max_iter) break;
+        }
+    } else {
+        Ctl* ctl32 = at<Ctl>(ws, L.off_ctl32);
+        Slot<float>* dslots32 = at<Slot<float>>(ws, L.off_slots32);
+        cx<float>* d32 = at<cx<float>>(ws, L.off_d32);
+        cx<float>* w32 = at<cx<float>>(ws, L.off_w32);
+        cx<float>* y32 = at<cx<float>>(ws, L.off_y32);
+        cx<float>* p32 = at<cx<float>>(ws, L.off_p32);
+        float* rb32 = at<float>(ws, L.off_rb32);
+        const SplitRun<float> r32 = split_run<float>(m, m->ps32, G, w32, p32, dslots32);
+        HIPOK(launch_relayout<float>(m->rhobar32, LAY_WHOLE, rb32, LAY_SLAB, 3, n, G, st));
+        HIPOK(launch_ctl_clear(ctl32, st));
+        {
+            std::vector<Slot<float>> hs(2 * G + 1);
+            split_slots<float>(m, r32, d32, y32, rb32, m->q32, m->gc32, m->gs32, m->kv32, m->sh32, ctl32,
+                               at<double>(ws, L.off_part32), at<double>(ws, L.off_chunk32), hs.data());
+            HIPOK(hipMemcpyAsync(dslots32, hs.data(), sizeof(Slot<float>) * hs.size(), hipMemcpyHostToDevice, st));
+            HIPOK(hipStreamSynchronize(st));
+        }
+        const double inner_tol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
+        const int max_outer = o->max_outer > 0 ? o->max_outer : 10000;
+        const int64_t max_inner = o->max_inner > 0 ? o->max_inner : 256;
+        int64_t total = 0;
+        for (int outer = 0;; ++outer) {
+            HIPOK(split_iteration<double>(r64, MODE_APPLY, true, st));
+            inf.residual_evals++;
+            if ((cs = read_ctl(m, ctl64, &hc, st)) != CBS_OK) return cs;
+            inf.rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
+            inf.outer = outer;
+            if (!std::isfinite(inf.rel_residual)) {
+                status = CBS_E_DIVERGED;
+                break;
+            }
+            if (inf.rel_residual <= o->tol) {
+                status = CBS_OK;
+                break;
+            }
+            if (outer >= max_outer || total >= o->max_iter) break;
+            HIPOK(launch_convert(w64, y32, nf, ctl64, st));
+            HIPOK(launch_zero<float>(d32, nf, st));
+            const int64_t cap = std::min<int64_t>(o->max_iter - total, max_inner);
+            HIPOK(launch_ctl_reset(ctl32, (int)cap, inner_tol, st));
+            Ctl ic{};
+            int64_t launched = 0;
+            while (true) {
+                const int64_t chunk = std::min<int64_t>(check, cap - launched);
+                for (int64_t k = 0; k < chunk; ++k)
+                    HIPOK(split_iteration<float>(r32, MODE_CBS, launched + k == 0, st));
+                launched += chunk;
+                if ((cs = read_ctl(m, ctl32, &ic, st)) != CBS_OK) return cs;
+                if (ic.done != RUNNING || launched >= cap) break;
+            }
+            total += ic.iter;
+            inf.rel_update = ic.rel_update;
+            if (ic.done == DIVERGED) {
+                status = CBS_E_DIVERGED;
+                break;
+            }
+            HIPOK(launch_accumulate(x64, d32, nf, ctl64, st));
+        }
+        inf.iterations = total;
+    }
+    if (status != CBS_E_DIVERGED) {
+        // the parts' state back in the whole-grid layout, then unscaled out
+        HIPOK(launch_relayout<cx<double>>(x64, LAY_SLAB, p64, LAY_WHOLE, 4, n, G, st));
+        if ((cs = write_outputs<double>(m, p64, p_out, u_out, o->ptr_kind, w64, st)) != CBS_OK) return cs;
+    }
+    inf.status = status;
+    inf.seconds = now_s() - t0;
+    if (info) *info = inf;
+    return (cbs_status)status;
+}
+
+}  // namespace
+
+extern "C" {
+
+cbs_status cbs_split_workspace_bytes(cbs_medium m, int32_t prec, int32_t parts, size_t* bytes) {
+    const cbs_status cs = split_check(m, parts);
+    if (cs != CBS_OK) return cs;
+    if (!bytes || (prec != CBS_FP64 && prec != CBS_FP32_REFINED)) return CBS_E_INVALID;
+    *bytes = split_layout_for(m->g, prec, parts).total;
+    return CBS_OK;
+}
+
+cbs_status cbs_solve_split(cbs_medium m, int32_t parts, const void* s_p, const void* s_u,
+                           const cbs_solve_opts* opts, void* p_out, void* u_out, void* workspace, size_t ws_bytes,
+                           cbs_solve_info* info, void* hip_stream) {
+    return guarded(
+        [&] { return solve_split_impl(m, parts, s_p, s_u, opts, p_out, u_out, workspace, ws_bytes, info, hip_stream); });
+}
+
+}  // extern "C"

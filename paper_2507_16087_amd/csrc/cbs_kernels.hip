@@ -129,6 +129,74 @@ __global__ void k_ctl_clear(Ctl* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = Ctl{};
 }
 
+// ------------------------------------------------------ slab exchange --
+// Layouts of F planes of an n0 x n1 x n2 grid split into G parts:
+//   0 whole grid      [f][i0][i1][i2]
+//   1 axis-0 slabs    part g = i0 / s (s = n0 / G): [g][f][i0 % s][i1][i2]
+//   2 axis-1 pencils  part h = i1 / t (t = n1 / G): [h][f][i0][i1 % t][i2]
+// k_relayout copies every element from one layout to another, walking the
+// destination in memory order; from layout 1 to 2 and back it is the
+// all-to-all exchange of a solve split over G devices.
+struct SplitDims {
+    int F, n0, n1, n2, G;
+};
+
+__device__ __forceinline__ int64_t split_offset(int lay, const SplitDims& d, int f, int i0, int i1, int i2) {
+    if (lay == 0) return (((int64_t)f * d.n0 + i0) * d.n1 + i1) * d.n2 + i2;
+    if (lay == 1) {
+        const int s = d.n0 / d.G;
+        return (int64_t)(i0 / s) * d.F * s * d.n1 * d.n2 + (((int64_t)f * s + i0 % s) * d.n1 + i1) * d.n2 + i2;
+    }
+    const int t = d.n1 / d.G;
+    return (int64_t)(i1 / t) * d.F * d.n0 * t * d.n2 + (((int64_t)f * d.n0 + i0) * t + i1 % t) * d.n2 + i2;
+}
+
+__device__ __forceinline__ void split_coords(int lay, const SplitDims& d, int64_t e, int* f, int* i0, int* i1,
+                                             int* i2) {
+    if (lay == 0) {
+        *i2 = (int)(e % d.n2);
+        e /= d.n2;
+        *i1 = (int)(e % d.n1);
+        e /= d.n1;
+        *i0 = (int)(e % d.n0);
+        *f = (int)(e / d.n0);
+    } else if (lay == 1) {
+        const int s = d.n0 / d.G;
+        const int64_t part = (int64_t)d.F * s * d.n1 * d.n2;
+        const int g = (int)(e / part);
+        e %= part;
+        *i2 = (int)(e % d.n2);
+        e /= d.n2;
+        *i1 = (int)(e % d.n1);
+        e /= d.n1;
+        *i0 = g * s + (int)(e % s);
+        *f = (int)(e / s);
+    } else {
+        const int t = d.n1 / d.G;
+        const int64_t part = (int64_t)d.F * d.n0 * t * d.n2;
+        const int h = (int)(e / part);
+        e %= part;
+        *i2 = (int)(e % d.n2);
+        e /= d.n2;
+        *i1 = h * t + (int)(e % t);
+        e /= t;
+        *i0 = (int)(e % d.n0);
+        *f = (int)(e / d.n0);
+    }
+}
+
+template <typename E>
+__global__ void __launch_bounds__(256) k_relayout(const E* __restrict__ src, int src_lay, E* __restrict__ dst,
+                                                  int dst_lay, SplitDims d) {
+    const int64_t total = (int64_t)d.F * d.n0 * d.n1 * d.n2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int f, i0, i1, i2;
+        split_coords(dst_lay, d, e, &f, &i0, &i1, &i2);
+        dst[e] = src[split_offset(src_lay, d, f, i0, i1, i2)];
+    }
+}
+
 // Per-pencil flags of a sparse right-hand side: flag[k] = 1 if any of the n
 // values of pencil k (of one field plane) is non-zero.  One wave per pencil.
 __global__ void __launch_bounds__(256) k_pencil_flags(const cx<double>* __restrict__ plane, int64_t pencils, int n,
@@ -377,6 +445,22 @@ hipError_t launch_ctl_clear(Ctl* c, hipStream_t st) {
     hipLaunchKernelGGL(k_ctl_clear, dim3(1), dim3(64), 0, st, c);
     return hipGetLastError();
 }
+
+template <typename E>
+hipError_t launch_relayout(const E* src, int src_lay, E* dst, int dst_lay, int F, const int* n, int G,
+                           hipStream_t st) {
+    const SplitDims d{F, n[0], n[1], n[2], G};
+    const int64_t total = (int64_t)F * n[0] * n[1] * n[2];
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_relayout<E>), dim3(blocks), dim3(256), 0, st, src, src_lay, dst, dst_lay, d);
+    return hipGetLastError();
+}
+template hipError_t launch_relayout<cx<double>>(const cx<double>*, int, cx<double>*, int, int, const int*, int,
+                                                hipStream_t);
+template hipError_t launch_relayout<cx<float>>(const cx<float>*, int, cx<float>*, int, int, const int*, int,
+                                               hipStream_t);
+template hipError_t launch_relayout<double>(const double*, int, double*, int, int, const int*, int, hipStream_t);
+template hipError_t launch_relayout<float>(const float*, int, float*, int, int, const int*, int, hipStream_t);
 
 hipError_t launch_pencil_flags(const cx<double>* plane, int64_t pencils, int n, unsigned char* flag,
                                hipStream_t st) {

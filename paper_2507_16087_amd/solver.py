@@ -216,6 +216,45 @@ def solve(m: Medium, s_p, s_u=None, *, tol=1e-8, max_iter=100000, prec="fp64", c
     return p, u, d
 
 
+def solve_split(m: Medium, parts: int, s_p, s_u=None, *, tol=1e-8, max_iter=100000, prec="fp64",
+                check_every=32, inner_tol=0.0, stop_rule=L.CBS_STOP_UPDATE, max_outer=0, max_inner=0,
+                want_u=True, stream=None):
+    """The solve of :func:`solve` split into `parts` axis-0 slabs the way
+    that many GPUs would run it (cbs_solve_split), on the current device.
+    Returns (p, u, info) like :func:`solve`."""
+    torch = _torch()
+    device = _is_tensor(s_p)
+    N = m.ncell
+    if device:
+        sp = _dev_c128(s_p.reshape(-1), N)
+        su = _dev_c128(s_u.reshape(-1), m.ndim * N) if s_u is not None else None
+        p = torch.empty(N, dtype=torch.complex128, device=sp.device)
+        u = torch.empty(m.ndim * N, dtype=torch.complex128, device=sp.device) if want_u else None
+        kind = L.CBS_PTR_DEVICE
+    else:
+        sp = _host_c128(s_p, N)
+        su = _host_c128(s_u, m.ndim * N)
+        p = np.empty(N, np.complex128)
+        u = np.empty(m.ndim * N, np.complex128) if want_u else None
+        kind = L.CBS_PTR_HOST
+    nb = C.c_size_t()
+    L.check(L.lib().cbs_split_workspace_bytes(m.handle, PREC[prec], int(parts), C.byref(nb)),
+            "cbs_split_workspace_bytes")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    o = _opts(tol, max_iter, prec, check_every, inner_tol, L.CBS_RHS_PHYSICAL, kind, stop_rule, max_outer,
+              max_inner)
+    info = L.SolveInfo()
+    st = L.lib().cbs_solve_split(m.handle, int(parts), _ptr(sp), _ptr(su), C.byref(o), _ptr(p), _ptr(u),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), C.byref(info), _stream_ptr(stream))
+    L.check(st, "cbs_solve_split", (L.CBS_OK, L.CBS_NOT_CONVERGED))
+    d = info.as_dict()
+    d["converged"] = st == L.CBS_OK
+    p = p.reshape(m.shape)
+    if u is not None:
+        u = u.reshape((m.ndim,) + m.shape)
+    return p, u, d
+
+
 def residual(m: Medium, s_p, s_u, p, u=None, *, adjoint=False, equation_rhs=False,
              want_fields=False, workspace=None, stream=None):
     """Scaled FP64 residual |y - (L+V) x| / |y|; optionally the physical
