@@ -10,14 +10,23 @@ before the timed region.
 
 Prints one JSON line.  Fields beyond the driver contract:
   time_to_tol_ms   -- wall time per solve, refined FP32 and plain FP64
+  time_to_accuracy -- both paths solved to a scaled residual of 1e-7 (where
+                      the shell's error falls below 1e-5), with their errors
+                      against an FP64 GPU solve to 1e-8 (the oracle cannot
+                      converge a 256^3 solve on the host in useful time)
   iterations       -- CBS iterations per solve, each path
-  passes           -- per-pass average duration (HIP events) and achieved GB/s
+  passes           -- per-pass average duration (HIP events), achieved GB/s and
+                      fraction of the 8 TB/s peak; lowest_pass names the slowest
+                      against its bytes
   roofline         -- dominant kernel against the 8 TB/s HBM peak
   cpu_baseline     -- the FP64 oracle on a bounded sample of the same workload
   pressure_rel_diff_refined_vs_fp64 -- relative L2 distance of the two solves'
                       pressure fields (both stopped at the same FP64 residual)
   medium_setup_s   -- host planning and upload of the medium (outside the timed region)
   serving, p50_ms, p99_ms -- the request-stream leg (mixed sizes, continuous batching)
+  serving_tight_budget -- the same stream with an HBM budget of three times one
+                      192^3 request's footprint and three-slot pools, so
+                      admission waits on memory
 """
 from __future__ import annotations
 
@@ -49,8 +58,10 @@ def _kernel_suffix(pass_name, plan):
     """Trailing template arguments that name this pass's kernel instance in a
     rocprofv3 summary (mode, kind / direction, variant, precision)."""
     v = plan.get("variant", 0) if plan else 0
-    return {"inv_axis2_update_fwd_axis2": ("k_lastaxis", f", 0, 2, {v}, float>"),
-            "axis0_propagator": ("k_prop", f", 0, {v}, float>"),
+    # k_lastaxis<Plan, mode, kind, prefetch, sparse y, T>; k_prop<Plan, mode,
+    # LDS layout (variant bits 0-1), ndim, T>
+    return {"inv_axis2_update_fwd_axis2": ("k_lastaxis", f", 0, 2, {v & 3}, false, float>"),
+            "axis0_propagator": ("k_prop", f", 0, {v & 3}, 3, float>"),
             "fwd_axis1": ("k_strided", ", -1, float>"),
             "inv_axis1": ("k_strided", ", 1, float>")}.get(pass_name)
 
@@ -60,10 +71,9 @@ def committed_traffic(pass_name, plan):
     counter summary, or None if the kernels changed since it was taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "shell256_traffic.txt")
-    src = os.path.join(ROOT, "paper_2507_16087_amd", "csrc", "cbs_kernels.hip")
     if not os.path.exists(prof):
         return None
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    cur = kernel_source_hash()
     text = open(prof).read()
     if f"sha256[:16]: {cur}" not in text:
         return None
@@ -77,6 +87,15 @@ def committed_traffic(pass_name, plan):
         if want[1] in line:
             return float(line.split()[-2])
     return None
+
+
+def kernel_source_hash() -> str:
+    """sha256[:16] of the pass kernels' source (templates and plan table)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("cbs_passes.h", "cbs_plans.h"):
+        h.update(open(os.path.join(ROOT, "paper_2507_16087_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -99,34 +118,101 @@ def oracle_baseline(prob, iters: int):
                        f"{'x'.join(map(str, prob.shape))} workload ({dt:.1f} s)")
 
 
-def serving_leg(n_requests: int, log_fn):
+def serving_leg(n_requests: int, log_fn, rate=None, budget=None, slots=4):
     """Mixed-size request stream (64^3..192^3 random media, 0.25-1 MHz, refined
-    FP32 to 1e-5) through the continuous-batching server.  A burst of the
-    first requests measures capacity; the stream then arrives as a Poisson
-    process at 0.8 of that capacity."""
+    FP32 to 1e-5) through the continuous-batching server.  Without a given
+    rate, a burst of the first requests measures capacity and the stream
+    then arrives as a Poisson process at 0.8 of that capacity.  `budget`
+    (bytes) caps the server's HBM admission budget; `slots` is the number of
+    slots per shape pool (a pool's workspace is sized for all of them)."""
     from paper_2507_16087_amd import workloads as W
     from paper_2507_16087_amd.serve import Server
-    probe = W.request_stream(count=min(16, n_requests), rate_hz=1e6, seed=4242)
     t0 = time.perf_counter()
-    cap = Server(tol=1e-5, slots_per_pool=4, step_iters=32).run(probe)
-    log_fn(f"serving capacity probe: {len(probe)} solves in {cap['wall_s']:.2f} s "
-           f"({cap['solves_per_s']:.2f}/s)")
-    rate = 0.8 * cap["solves_per_s"]
+    cap_rate = None
+    if rate is None:
+        probe = W.request_stream(count=min(16, n_requests), rate_hz=1e6, seed=4242)
+        cap = Server(tol=1e-5, slots_per_pool=4, step_iters=32).run(probe)
+        log_fn(f"serving capacity probe: {len(probe)} solves in {cap['wall_s']:.2f} s "
+               f"({cap['solves_per_s']:.2f}/s)")
+        cap_rate = cap["solves_per_s"]
+        rate = 0.8 * cap_rate
     reqs = W.request_stream(count=n_requests, rate_hz=rate, seed=4242)
-    out = Server(tol=1e-5, slots_per_pool=4, step_iters=32).run(reqs)
-    log_fn(f"serving: {n_requests} requests at {rate:.2f}/s: p50 {out['p50_ms']:.0f} ms, "
-           f"p99 {out['p99_ms']:.0f} ms, {out['solves_per_s']:.2f} solves/s, "
-           f"{time.perf_counter() - t0:.1f} s total")
-    sizes = {}
-    for r in out["results"]:
-        sizes.setdefault(r.shape[0], []).append(r.latency * 1e3)
-    return {"requests": n_requests, "arrival_rate_hz": round(rate, 3),
-            "capacity_probe_solves_per_s": round(cap["solves_per_s"], 3),
-            "p50_ms": round(out["p50_ms"], 1), "p99_ms": round(out["p99_ms"], 1),
-            "solves_per_s": round(out["solves_per_s"], 3), "converged": out["converged"],
-            "max_concurrency": out["max_concurrency"],
-            "p50_ms_by_size": {str(k): round(float(np.median(v)), 1) for k, v in sorted(sizes.items())},
-            "precision": "fp32 inner, fp64 refinement, tol 1e-5"}
+    out = Server(tol=1e-5, slots_per_pool=slots, step_iters=32, hbm_budget=budget).run(reqs)
+    log_fn(f"serving: {n_requests} requests at {rate:.2f}/s, budget {out['budget_bytes'] / 1e9:.2f} GB: "
+           f"p50 {out['p50_ms']:.0f} ms, p99 {out['p99_ms']:.0f} ms, {out['solves_per_s']:.2f} solves/s, "
+           f"{out['memory_waits']} waited on memory, {time.perf_counter() - t0:.1f} s total")
+    res = {"requests": n_requests, "arrival_rate_hz": round(rate, 3),
+           "p50_ms": round(out["p50_ms"], 1), "p99_ms": round(out["p99_ms"], 1),
+           "solves_per_s": round(out["solves_per_s"], 3), "converged": out["converged"],
+           "failed": out["failed"], "max_concurrency": out["max_concurrency"],
+           "by_size": {k: {"count": v["count"], "p50_ms": round(v["p50_ms"], 1),
+                           "p99_ms": round(v["p99_ms"], 1)} for k, v in out["by_size"].items()},
+           "hbm_budget_gb": round(out["budget_bytes"] / 1e9, 3),
+           "requests_that_waited_on_memory": out["memory_waits"],
+           "budget_bound": out["memory_waits"] > 0,
+           "pool_evictions": out["pool_evictions"], "slots_per_pool": slots,
+           "precision": "fp32 inner, fp64 refinement, tol 1e-5"}
+    if cap_rate is not None:
+        res["capacity_probe_solves_per_s"] = round(cap_rate, 3)
+    return res
+
+
+def accuracy_leg(solver, _lib, m, sp, ws32, ws64, args, log_fn):
+    """Time-to-accuracy: refined FP32 and plain FP64 each solved to a scaled
+    residual of args.acc_tol (timed), and their pressure errors against an FP64
+    solve to args.ref_tol (untimed).  On the ill-conditioned shell the error
+    is tens of times the residual, so a residual of 1e-7 is what an error
+    below 1e-5 takes."""
+    import torch
+    res = {"residual": args.acc_tol, "reference": f"fp64 GPU solve to residual {args.ref_tol:g}"}
+    ref, _, iref = solver.solve(m, sp, tol=args.ref_tol, prec="fp64", check_every=200,
+                                stop_rule=_lib.CBS_STOP_RESIDUAL, workspace=ws64, want_u=False,
+                                max_iter=400000)
+    log_fn(f"accuracy reference: fp64 to {args.ref_tol:g}: {iref['iterations']} it")
+    res["reference_iterations"] = iref["iterations"]
+    for name, prec, ws in (("fp32_refined", "fp32_refined", ws32), ("fp64_plain", "fp64", ws64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kw = dict(stop_rule=_lib.CBS_STOP_RESIDUAL) if prec == "fp64" else {}
+        pp, _, inf = solver.solve(m, sp, tol=args.acc_tol, prec=prec, check_every=args.check_every,
+                                  workspace=ws, want_u=False, max_iter=400000, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(pp - ref) / torch.linalg.vector_norm(ref))
+        log_fn(f"accuracy {name}: {inf['iterations']} it, {t:.2f} s, error {err:.2e}")
+        res[name] = {"ms": round(t * 1e3, 2), "iterations": inf["iterations"],
+                     "rel_residual": inf["rel_residual"], "pressure_error": err}
+        del pp
+    res["speedup_refined_vs_fp64"] = round(res["fp64_plain"]["ms"] / res["fp32_refined"]["ms"], 3)
+    del ref
+    return res
+
+
+def split_only(args, solver, m, sp, prob, setup_s):
+    """Refined solves split over args.split axis-0 slabs (cbs_solve_split) in
+    place of the whole-grid solves: every pass runs per part at the part's
+    shape, with device copies standing for the exchanges between parts."""
+    import torch
+    kw = dict(tol=args.tol, prec="fp32_refined", check_every=args.check_every, inner_tol=args.inner_tol,
+              want_u=True, max_iter=args.max_iter)
+    for i in range(args.warmup):
+        solver.solve_split(m, args.split, sp, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for i in range(args.steps):
+        _, _, info = solver.solve_split(m, args.split, sp, **kw)
+        iters += info["iterations"]
+        log(f"split step {i}: {info['iterations']} it, res {info['rel_residual']:.2e}, {info['seconds']:.2f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({
+        "metric": "Gcell-iter/s, solve split over axis-0 slabs on one GPU", "value": round(prob.ncell * iters / dt / 1e9, 4),
+        "unit": "Gcell-iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"shell3d_{args.n}", "parts": args.split, "tol": args.tol},
+        "medium_setup_s": round(setup_s, 3)}), flush=True)
 
 
 def main():
@@ -143,6 +229,14 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tight-serve", action="store_true")
+    ap.add_argument("--split", type=int, default=0,
+                    help="time the solve split over this many axis-0 slabs the way that many GPUs would run "
+                         "it, on this one GPU (kernel-trace profiling of the per-part passes)")
+    ap.add_argument("--acc-tol", type=float, default=1e-7,
+                    help="residual of the time-to-accuracy leg (0 skips it)")
+    ap.add_argument("--ref-tol", type=float, default=1e-8,
+                    help="residual of the FP64 reference of the time-to-accuracy leg")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="cap on inner iterations per solve (short profiling runs)")
     args = ap.parse_args()
@@ -164,6 +258,9 @@ def main():
                       pml=prob.pml_cells)
     setup_s = time.perf_counter() - t0
     sp = torch.from_numpy(prob.dense_source().ravel()).to(dev)
+    if args.split:
+        split_only(args, solver, m, sp, prob, setup_s)
+        return
     ws32 = m.workspace("fp32_refined")
     common = dict(tol=args.tol, prec="fp32_refined", check_every=args.check_every,
                   inner_tol=args.inner_tol, workspace=ws32, want_u=True, max_iter=args.max_iter)
@@ -205,7 +302,8 @@ def main():
         per_iter = ms[k] / cnt[k] * blocks[k]
         gbs = PASS_BYTES_F32[k] * prob.ncell / (per_iter * 1e-3) / 1e9
         passes[name] = dict(avg_ms=round(per_iter, 5), launches=int(cnt[k]), column_blocks=blocks[k],
-                            achieved_gbs=round(gbs, 1), bytes_per_cell=PASS_BYTES_F32[k])
+                            achieved_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4),
+                            bytes_per_cell=PASS_BYTES_F32[k])
         if best is None or ms[k] > ms[best]:
             best = k
     total_pass_ms = sum(ms[k] for k in range(6))
@@ -256,6 +354,7 @@ def main():
         "final_residual": {"fp32_refined": infos[-1]["rel_residual"]},
         "medium_setup_s": round(setup_s, 3),
         "passes": passes,
+        "lowest_pass": min(passes, key=lambda k: passes[k]["frac"]) if passes else None,
         "passes_note": ("per-pass HIP-event times per iteration (summed over column blocks) from one "
                         "extra solve outside the timed region"),
         "fp64_residual_pass_ms": fp64_res,
@@ -292,14 +391,30 @@ def main():
         out["final_residual"]["fp64_plain"] = i64["rel_residual"]
         out["gcell_iter_s_fp64"] = round(prob.ncell * i64["iterations"] / t64 / 1e9, 4)
         out["speedup_refined_vs_fp64"] = round(t64 / (dt / args.steps), 3)
+        del p64
+
+        if args.acc_tol > 0:
+            out["time_to_accuracy"] = accuracy_leg(solver, _lib, m, sp, ws32, ws64, args, log)
         del ws64
 
     if not args.no_serve:
-        del ws32
+        del ws32, p, u
+        m = None
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(args.serve_requests, log)
         out["p50_ms"] = out["serving"]["p50_ms"]
         out["p99_ms"] = out["serving"]["p99_ms"]
+        if not args.no_tight_serve:
+            from paper_2507_16087_amd.serve import Server
+            # three times what one 192^3 request needs alone (a one-slot pool's
+            # workspace and its medium); pools of three slots, so an open
+            # 192^3 pool leaves room for little beside it
+            probe = Server(tol=1e-5, slots_per_pool=1)
+            budget = 3 * probe.footprint((192, 192, 192), True)
+            del probe
+            out["serving_tight_budget"] = serving_leg(args.serve_requests, log,
+                                                      rate=out["serving"]["arrival_rate_hz"],
+                                                      budget=budget, slots=3)
         ws32 = None
 
     if not args.no_cpu:
