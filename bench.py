@@ -157,6 +157,38 @@ def serving_leg(n_requests: int, log_fn, rate=None, budget=None, slots=4):
     return res
 
 
+def copy_ceiling(torch, _lib, nbytes: int = 2 << 30, reps: int = 10) -> dict:
+    """Streaming rate a plain copy reaches here (the library's hand-written
+    probe: nbytes read and nbytes written per launch, contiguous 16 KiB chunks
+    per work-group, nontemporal accesses; and, beside it, the HIP runtime's
+    device-to-device copy, timed with HIP events on torch's stream): the
+    practical ceiling of an HBM-bound pass that reads and writes in equal
+    measure, beside the published peak."""
+    import ctypes as C
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    gbs = C.c_double(0.0)
+    st = torch.cuda.current_stream().cuda_stream
+    _lib.check(_lib.lib().cbs_stream_probe(a.data_ptr(), b.data_ptr(), nbytes, reps, C.byref(gbs), st),
+               "cbs_stream_probe")
+    assert torch.equal(a, b)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    rt = 2 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": 2 * nbytes, "achieved_gbs": round(gbs.value, 1),
+            "frac": round(gbs.value / HBM_PEAK_GBS, 4), "hip_runtime_copy_gbs": round(rt, 1),
+            "kernel": "cbs_stream_probe (16 KiB contiguous chunk per work-group, nontemporal)"}
+
+
 def accuracy_leg(solver, _lib, m, sp, ws32, ws64, args, log_fn):
     """Time-to-accuracy: refined FP32 and plain FP64 each solved to a scaled
     residual of args.acc_tol (timed), and their pressure errors against an FP64
@@ -372,6 +404,12 @@ def main():
                            "kernel": PASS_NAMES[k],
                            "bytes_per_launch": PASS_BYTES_F32[k] * prob.ncell // blocks[k],
                            "avg_launch_ms": round(avg, 5), "launches": int(cnt_t[k])}
+    out["hbm_copy"] = copy_ceiling(torch, _lib)
+    if "roofline" in out:
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / out["hbm_copy"]["achieved_gbs"], 4)
+    for v in passes.values():
+        v["frac_of_copy"] = round(v["achieved_gbs"] / out["hbm_copy"]["achieved_gbs"], 4)
+    log(f"plain copy: {out['hbm_copy']['achieved_gbs']} GB/s")
 
     if not args.no_fp64:
         ws64 = m.workspace("fp64")

@@ -300,6 +300,19 @@ cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
  * one launch per block. */
 cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18]);
 
+/* Streaming-bandwidth probe for measurement: copies `bytes` from src to dst
+ * (device pointers, 16-byte aligned, non-overlapping; bytes a non-zero
+ * multiple of 16) once to warm up and then reps times on hip_stream (null:
+ * the default stream), each work-group one contiguous 16 KiB chunk with
+ * nontemporal loads and stores, and writes 2 * bytes / (average copy time)
+ * in GB/s to *gbs: the rate a kernel that reads and writes HBM in equal
+ * measure reaches on this device, beside which the passes' rates can be
+ * read.  Blocks until done.  CBS_E_INVALID for a null, misaligned or
+ * overlapping pointer, a bad size or reps < 1; CBS_E_DEVICE for a HIP
+ * failure. */
+cbs_status cbs_stream_probe(const void *src, void *dst, size_t bytes, int32_t reps, double *gbs,
+                            void *hip_stream);
+
 /* ---------------- batched slots (continuous-batching serving) -------------
  * A batch runs same-shape solves side by side: one kernel launch per pass
  * covers every active slot, iterations are captured in a HIP graph per

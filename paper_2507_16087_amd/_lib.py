@@ -38,7 +38,7 @@ EXPORTS = [
     "cbs_pass_config", "cbs_pass_timing", "cbs_pass_timing_slots", "cbs_pass_timing_read",
     "cbs_batch_workspace_bytes", "cbs_batch_create", "cbs_batch_destroy", "cbs_batch_submit",
     "cbs_batch_step", "cbs_batch_retire", "cbs_residual_noalloc", "cbs_split_workspace_bytes",
-    "cbs_solve_split",
+    "cbs_solve_split", "cbs_stream_probe",
 ]
 
 
@@ -95,6 +95,7 @@ def lib() -> C.CDLL:
     L.cbs_pass_timing.argtypes = [vp, i32]
     L.cbs_pass_timing_slots.argtypes = [vp, i32]
     L.cbs_pass_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    L.cbs_stream_probe.argtypes = [vp, vp, C.c_size_t, i32, dp, vp]
     L.cbs_batch_workspace_bytes.argtypes = [C.POINTER(Grid), i32, i32, C.POINTER(C.c_size_t)]
     L.cbs_batch_create.argtypes = [C.POINTER(Grid), i32, i32, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.cbs_batch_destroy.argtypes = [vp]

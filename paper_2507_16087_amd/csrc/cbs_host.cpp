@@ -33,6 +33,7 @@ template <typename T>
 hipError_t launch_reduce(bool cbs_mode, const Slot<T>* slots, int nparts, int nslots, hipStream_t st);
 hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st);
 hipError_t launch_ctl_clear(Ctl* c, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_pencil_flags(const cx<double>* plane, int64_t pencils, int n, unsigned char* flag,
                                hipStream_t st);
 template <typename T>
@@ -1630,9 +1631,16 @@ cbs_status residual_impl(cbs_medium m, const void* s_p, const void* s_u, const v
     else HIPOK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
     Slot<double> h = make_slot<double>(m, x, w, y, ctl, part, adjoint ? 1 : 0, at<double>(workspace, L.off_chunk64));
     HIPOK(hipMemcpyAsync(dslot, &h, sizeof(h), hipMemcpyHostToDevice, st));
-    HIPOK(run_passes<double>(m, ps, MODE_APPLY, dslot, 1, st));
+    // the allocation-free path never records pass timing (its events would be
+    // created on first use)
+    HIPOK(run_passes_set<double>(g, no_alloc ? nullptr : &m->timing, ps, MODE_APPLY, dslot, 1, dslot, 1, st));
     Ctl hc{};
-    if ((cs = read_ctl(m, ctl, &hc, st)) != CBS_OK) return cs;
+    if (no_alloc) {
+        HIPOK(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+    } else if ((cs = read_ctl(m, ctl, &hc, st)) != CBS_OK) {
+        return cs;
+    }
     if (rel_residual) *rel_residual = hc.rhs2 > 0 ? std::sqrt(hc.res2 / hc.rhs2) : 0.0;
     if (r_p || r_u) {
         const double sl1 = std::sqrt(m->lam1), sl2 = std::sqrt(m->lam2);
@@ -1774,6 +1782,31 @@ cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18
             ms[g * 6 + k] = m->timing.ms[g][k];
             launches[g * 6 + k] = m->timing.cnt[g][k];
         }
+    return CBS_OK;
+}
+
+cbs_status cbs_stream_probe(const void* src, void* dst, size_t bytes, int32_t reps, double* gbs,
+                            void* hip_stream) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+    if (!src || !dst || !gbs || (a | b) % 16 || bytes == 0 || bytes % 16 || reps < 1) return CBS_E_INVALID;
+    if ((a < b && b - a < bytes) || (b <= a && a - b < bytes)) return CBS_E_INVALID;   // overlapping
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CBS_E_DEVICE;
+    }
+    bool ok = launch_stream_copy(src, dst, bytes, st) == hipSuccess;   // warm-up
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = launch_stream_copy(src, dst, bytes, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return CBS_E_DEVICE;
+    *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
     return CBS_OK;
 }
 

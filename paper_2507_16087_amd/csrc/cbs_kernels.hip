@@ -441,6 +441,35 @@ hipError_t launch_ctl_reset(Ctl* c, int max_iter, double tol, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Streaming copy for bandwidth measurement: work-group b copies the b-th
+// contiguous chunk of kProbeChunk 16-byte vectors, four nontemporal loads in
+// flight per thread before their stores.
+constexpr size_t kProbeChunk = 1024;   // 16 KiB
+using v4u = unsigned int __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_stream_copy(const v4u* __restrict__ src, v4u* __restrict__ dst, size_t n) {
+    const size_t base = (size_t)blockIdx.x * kProbeChunk;
+    const size_t end = base + kProbeChunk < n ? base + kProbeChunk : n;
+    size_t i = base + threadIdx.x;
+    for (; i + 768 < end; i += 1024) {
+        const v4u a = __builtin_nontemporal_load(src + i), b = __builtin_nontemporal_load(src + i + 256);
+        const v4u c = __builtin_nontemporal_load(src + i + 512), d = __builtin_nontemporal_load(src + i + 768);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + 256);
+        __builtin_nontemporal_store(c, dst + i + 512);
+        __builtin_nontemporal_store(d, dst + i + 768);
+    }
+    for (; i < end; i += 256) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / sizeof(v4u);
+    const size_t grid = (n + kProbeChunk - 1) / kProbeChunk;
+    if (n == 0 || grid > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)grid), dim3(256), 0, st, static_cast<const v4u*>(src),
+                       static_cast<v4u*>(dst), n);
+    return hipGetLastError();
+}
+
 hipError_t launch_ctl_clear(Ctl* c, hipStream_t st) {
     hipLaunchKernelGGL(k_ctl_clear, dim3(1), dim3(64), 0, st, c);
     return hipGetLastError();

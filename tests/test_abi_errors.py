@@ -106,3 +106,21 @@ def test_batch_workspace_size_query_on_cpu():
     assert 288 <= per_cell < 320
     assert L.lib().cbs_batch_workspace_bytes(C.byref(g), 7, 4, C.byref(b)) == L.CBS_E_INVALID
     assert L.lib().cbs_batch_workspace_bytes(C.byref(g), 0, 0, C.byref(b)) == L.CBS_E_INVALID
+
+
+@pytest.mark.parametrize("src,dst,nbytes,reps", [
+    (0, 1 << 20, 64, 1),             # null source
+    (1 << 20, 0, 64, 1),             # null destination
+    ((1 << 20) + 8, 1 << 21, 64, 1),   # misaligned source
+    (1 << 20, (1 << 21) + 4, 64, 1),   # misaligned destination
+    (1 << 20, 1 << 21, 0, 1),        # no bytes
+    (1 << 20, 1 << 21, 40, 1),       # not a multiple of 16
+    (1 << 20, 1 << 21, 64, 0),       # no repetitions
+    (1 << 20, (1 << 20) + 32, 64, 1),  # destination inside the source
+    ((1 << 20) + 48, 1 << 20, 64, 1),  # source inside the destination
+])
+def test_stream_probe_rejects_bad_arguments(src, dst, nbytes, reps):
+    """The pointers are never dereferenced: every case fails its checks first."""
+    gbs = C.c_double(-1.0)
+    st = L.lib().cbs_stream_probe(C.c_void_p(src), C.c_void_p(dst), nbytes, reps, C.byref(gbs), None)
+    assert st == L.CBS_E_INVALID and gbs.value == -1.0
