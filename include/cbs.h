@@ -14,7 +14,7 @@
  * L + V of eqs. LV and C and the staggered (L+I)^{-1} of App. B.1).
  *
  * Conventions shared by every entry point
- *  - Grid: ndim in {2, 3}; n[eta] cells per axis, C order, last axis
+ *  - Grid: ndim in {1, 2, 3}; n[eta] cells per axis, C order, last axis
  *    contiguous.  Each n[eta] must be of the form 2^a 3^b with
  *    4 <= n[eta] <= 512 (4, 6, 8, 9, 12, 16, 18, 24, 27, ..., 384, 432, 486,
  *    512: one compiled FFT plan per length, a whole pencil in one
@@ -93,7 +93,7 @@ enum { CBS_RHS_PHYSICAL = 0, CBS_RHS_EQUATION = 1 };
 enum { CBS_STOP_UPDATE = 0, CBS_STOP_RESIDUAL = 1 };
 
 typedef struct {
-    int32_t ndim;            /* 2 or 3                                              */
+    int32_t ndim;            /* 1, 2 or 3                                           */
     int64_t n[3];            /* cells per axis (unused axes ignored)                */
     double dx;               /* grid spacing [m]                                    */
     double omega;            /* angular frequency [rad/s]                           */
@@ -263,7 +263,9 @@ cbs_status cbs_pass_timing_slots(cbs_medium m, int32_t slot_mask);
 
 /* Pass plans in use for precision prec (after the first solve tunes them):
  * out[4 i + 0..3] = kind, axis length, columns per work-group and flags of
- * pass i in launch order (kind -1 = unused).  Flags:
+ * pass i in launch order (kind -1 = unused; kinds 0 contiguous forward, 1
+ * contiguous inverse, 2 / 3 strided forward / inverse, 4 axis-0 propagator,
+ * 6 the operator alone on the spectrum of a 1-D grid).  Flags:
  *   bit 0     wide radix split (fewer elements per thread);
  *   bits 1-4  variant.  Propagator pass: LDS layout 0 one tile reused field
  *             by field, 1 one region per field with every exchange shared,
@@ -296,7 +298,8 @@ cbs_status cbs_pass_config(cbs_medium m, int32_t prec, int32_t out[20]);
  * CBS iteration, 1 FP64 CBS iteration, 2 FP64 residual) and slot k (0..4 the
  * passes in launch order -- contiguous forward, strided forward, axis-0
  * propagator, strided inverse, contiguous inverse; 2-D grids use slots 0, 1
- * and 4 -- and 5 the reduction).  Middle passes run in column blocks count
+ * and 4, 1-D grids slot 1 for the operator on the spectrum -- and 5 the
+ * reduction).  Middle passes run in column blocks count
  * one launch per block. */
 cbs_status cbs_pass_timing_read(cbs_medium m, double ms[18], int64_t launches[18]);
 

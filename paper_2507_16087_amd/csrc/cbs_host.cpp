@@ -77,7 +77,8 @@ bool size_supported(int64_t n) { return n >= 4 && n <= 512 && plan_tpc((int)n, f
 // The passes of one iteration, and the column-tile width of each.
 struct Pass {
     int kind;    // 0 contiguous forward (+prologue), 1 contiguous inverse (+epilogue),
-                 // 2 strided forward, 3 strided inverse, 4 axis-0 propagator
+                 // 2 strided forward, 3 strided inverse, 4 axis-0 propagator,
+                 // 6 operator alone on the spectrum (1-D grids)
     int axis;
     int n;
     int pcols;
@@ -138,7 +139,17 @@ PassSet make_passes(const Geom& g, bool fp64) {
     int k = 0;
     ps.p[k++] = contig(0);
     if (g.ndim == 3) ps.p[k++] = strided(2, 1, false);
-    ps.p[k++] = strided(4, 0, fp64);
+    if (g.ndim == 1) {
+        // one axis, the contiguous one: the operator alone on the spectrum
+        Pass p{};
+        p.kind = 6;
+        p.axis = 0;
+        p.n = g.n[0];
+        p.pcols = 1;
+        ps.p[k++] = p;
+    } else {
+        ps.p[k++] = strided(4, 0, fp64);
+    }
     if (g.ndim == 3) ps.p[k++] = strided(3, 1, false);
     ps.p[k++] = contig(1);
     ps.count = k;
@@ -724,6 +735,7 @@ cbs_status tune_set(cbs_medium_s* m, PassSet& ps, Slot<T>* dslot, cx<T>* x, cx<T
         const int kind = (i == ps.count - 1) ? 5 : ps.p[i].kind;
         float best = -1.f;
         Pass pick = ps.p[i];
+        if (ps.p[i].kind == 6) continue;   // one configuration
         for (const Pass& c : pass_candidates(m->g, ps.p[i], fp64)) {
             const float t = time_pass<T>(m, kind, dslot, c, st);
             if (t > 0.f && (best < 0.f || t < best)) {
@@ -841,6 +853,7 @@ bool plausible(const Geom& g, const PassSet& def, const PassSet& ps) {
     for (int i = 0; i < ps.count; ++i) {
         const Pass &p = ps.p[i], &d = def.p[i];
         if (p.kind != d.kind || p.axis != d.axis || p.n != d.n) return false;
+        if (p.kind == 6 && (p.pcols != 1 || p.wide || p.variant)) return false;
         if (p.wide && !plan_has_wide(p.n)) return false;
         const int tpc = plan_tpc(p.n, p.wide);
         if (p.pcols < 1 || (p.pcols & (p.pcols - 1)) || tpc <= 0 || p.pcols * tpc > 256) return false;
@@ -968,7 +981,7 @@ cbs_status ensure_tuned(cbs_medium_s* m, int prec, void* ws, hipStream_t st) {
 
 cbs_status validate_grid(const cbs_grid* g) {
     if (!g) return CBS_E_INVALID;
-    if (g->ndim != 2 && g->ndim != 3) return CBS_E_UNSUPPORTED;
+    if (g->ndim < 1 || g->ndim > 3) return CBS_E_UNSUPPORTED;
     if (!(g->dx > 0) || !(g->omega > 0) || !std::isfinite(g->dx) || !std::isfinite(g->omega))
         return CBS_E_INVALID;
     for (int d = 0; d < g->ndim; ++d) {

@@ -391,9 +391,53 @@ template <int G, typename T>
 hipError_t launch_group(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
                         int pcols, bool wide, int variant, hipStream_t st, int l0, int lw);
 
+// 1-D grids: the one axis is the contiguous one, so the per-wavevector
+// operator of pass C runs on its own between the forward (A) and inverse (E)
+// last-axis passes, one thread per wavenumber on the spectrum in w.  MODE CBS
+// applies (L+I)^{-1} of App. B.1 in its rank-one form with one velocity
+// field (conjugate transpose for the adjoint); MODE APPLY applies the scaled
+// staggered derivative block of L (negated for the adjoint).  1/n is folded
+// in as in pass C.
+template <int MODE, typename T>
+__global__ void __launch_bounds__(256) k_op1(const Slot<T>* __restrict__ slots, int n) {
+    const Slot<T>& s = slots[blockIdx.y];
+    if (MODE == CBS && s.ctl->done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cx<T>* w = s.w;
+    const cx<T> wu = w[i], wp = w[n + i];
+    const T k = s.kv[0][i];
+    const cx<T> gk = rmul(k, s.sh[0][i]);   // k S
+    const cx<T> t = cmulc(wu, gk);           // conj(k S) w_u
+    if constexpr (MODE == CBS) {
+        const bool adj = s.adjoint != 0;
+        const cx<T> ca = adj ? conjg(s.ca) : s.ca;
+        const cx<T> cp = adj ? conjg(s.cp) : s.cp;
+        const T ss = adj ? -s.s : s.s;
+        const cx<T> mu = {k * k + s.al12.re, adj ? -s.al12.im : s.al12.im};
+        const cx<T> imu = rmul(s.inv_ntot, cinv_fast(mu));
+        const cx<T> tm = cmul(t, imu), wpm = cmul(wp, imu);
+        // u = ca (w_u - k S t / mu) - i sig s k S w_p / mu ; p = -i sig s t / mu + cp w_p / mu
+        w[i] = cmul(ca, rmul(s.inv_ntot, wu) - cmul(gk, tm)) - cmul(gk, rmul(ss, mul_i(wpm)));
+        w[n + i] = cmul(cp, wpm) - rmul(ss, mul_i(tm));
+    } else {
+        const T c = (s.adjoint ? -s.inv_ntot : s.inv_ntot) / s.s;
+        w[i] = rmul(c, mul_i(cmul(gk, wp)));
+        w[n + i] = rmul(c, mul_i(t));
+    }
+}
+
 template <typename T>
 hipError_t launch_pass(int kind, int mode, const Slot<T>* slots, int nslots, const Geom& g, int axis, int n,
                        int pcols, bool wide, int variant, hipStream_t st, int l0, int lw) {
+    if (kind == 6) {
+        // 1-D operator pass (kind 6): the whole grid is one spectrum of n points
+        if (g.ndim != 1 || n != g.n[0] || (mode != CBS && sizeof(T) != 8)) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)((n + 255) / 256), (unsigned)nslots);
+        if (mode == CBS) hipLaunchKernelGGL((k_op1<CBS, T>), grid, dim3(256), 0, st, slots, n);
+        else hipLaunchKernelGGL((k_op1<APPLY, T>), grid, dim3(256), 0, st, slots, n);
+        return hipGetLastError();
+    }
     switch (plan_group(n)) {
 #define GROUP_LAUNCH(G_) \
     case G_: return launch_group<G_, T>(kind, mode, slots, nslots, g, axis, n, pcols, wide, variant, st, l0, lw);

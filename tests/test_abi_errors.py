@@ -68,6 +68,10 @@ def test_every_smooth_length_is_accepted():
         ones = np.ones(shape)
         s = solver.plan_scalars(shape, 1e-4, 6e6, ones * 1500, ones * 1000, ones * 0, pml=1)
         assert s["lam1"] > 0, n
+    for n in SMOOTH:   # 1-D grids
+        ones = np.ones(n)
+        s = solver.plan_scalars((n,), 1e-4, 6e6, ones * 1500, ones * 1000, ones * 0, pml=1)
+        assert s["lam1"] > 0, n
     for n in (5, 10, 14, 20, 40, 100, 1024):
         ones = np.ones((n, 4))
         with pytest.raises(Exception):
@@ -85,8 +89,9 @@ def test_invalid_grid(kw):
 
 def test_invalid_dimension_and_null_pointers():
     ones = np.ones((16, 16))
-    st, _ = _create(_grid((16, 16), ndim=1), ones, ones, ones)
-    assert st == L.CBS_E_UNSUPPORTED
+    for nd in (0, 4):
+        st, _ = _create(_grid((16, 16), ndim=nd), ones, ones, ones)
+        assert st == L.CBS_E_UNSUPPORTED
     h = C.c_void_p()
     g = _grid()
     assert L.lib().cbs_create_medium(C.byref(g), None, None, None, 0, None, C.byref(h)) == L.CBS_E_INVALID

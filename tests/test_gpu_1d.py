@@ -1,0 +1,168 @@
+"""1-D grids on the GPU, through the C ABI, against the FP64 oracle and a
+closed form.
+
+In one dimension the only axis is the contiguous one: an iteration is the
+last-axis forward pass (w = B x + y, forward FFT), the operator alone on the
+spectrum (the same per-wavevector (L+I)^{-1} of App. B.1, one velocity
+field) and the fused last-axis inverse pass (inverse FFT, update, next
+prologue).
+
+* planner scalars equal the oracle's to 1e-12;
+* FP64 iterates after 1, 7 and 60 iterations equal the oracle's to 1e-10,
+  forward and adjoint, lengths 4 .. 512 with radix-2/3 plans;
+* FP64 converged (1e-12) equal to 1e-10, with the same iteration count;
+* refined FP32 within 1e-5 of the oracle's converged solution;
+* the residual and gradient entry points equal the oracle's to 1e-12;
+* physics: a single-cell source of strength 2c/dx in a homogeneous medium
+  radiates unit-amplitude waves (Sec. 2.3.1 source amplitude, App. A
+  Green's function), the GPU solution against the closed form directly.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_16087_amd import workloads as W
+from parity_util import maxrel, rel
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+OMEGA = 2 * np.pi * 1e6
+DX = 1500.0 / 1e6 / 6
+LENGTHS = [4, 9, 96, 243, 512]
+
+
+@pytest.fixture(scope="module")
+def cbs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_16087_amd import solver
+    return solver
+
+
+def _rel(a, b):
+    return max(rel(a, b), maxrel(a, b))
+
+
+def _pair(orc, cbs, n, seed=3, pml=None):
+    shape = (n,)
+    pml = max(1, n // 12) if pml is None else pml
+    c, rho, alpha = W.small_random(shape, seed)
+    om = orc.OracleMedium(shape, DX, OMEGA, c, rho, alpha, pml=pml)
+    gm = cbs.Medium(shape, DX, OMEGA, c, rho, alpha, pml=pml)
+    return om, gm
+
+
+def _sources(n, seed=17):
+    rng = np.random.default_rng(seed)
+    s = np.zeros((2, n), complex)
+    idx = rng.choice(n, min(3, n), replace=False)
+    s[1, idx] = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+    s[0, idx[0]] = 0.3 - 0.1j
+    return s
+
+
+@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("rule", [0, 1])
+def test_planner_scalars_1d(orc, cbs, n, rule):
+    shape = (n,)
+    c, rho, alpha = W.small_random(shape, 5)
+    pml = max(1, n // 12)
+    om = orc.OracleMedium(shape, DX, OMEGA, c, rho, alpha, pml=pml, shift_rule=rule)
+    gm = cbs.Medium(shape, DX, OMEGA, c, rho, alpha, pml=pml, shift_rule=rule)
+    so, sg = om.scalars(), gm.scalars()
+    for k in ("a1", "a2", "lam1", "lam2"):
+        assert abs(so[k] - sg[k]) <= 1e-12 * abs(so[k]), (k, so[k], sg[k])
+
+
+@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("iters", [1, 7, 60])
+def test_fp64_iterates_1d(orc, cbs, n, adjoint, iters):
+    om, gm = _pair(orc, cbs, n)
+    s = _sources(n)
+    xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=iters, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[1], s[:1], tol=0.0, max_iter=iters, adjoint=adjoint)
+    assert info["iterations"] == iters
+    assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
+    assert gm.pass_config("fp64")[1]["kind"] == 6
+
+
+@pytest.mark.parametrize("n", [96, 512])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_fp64_converged_1d(orc, cbs, n, adjoint):
+    om, gm = _pair(orc, cbs, n)
+    s = _sources(n, 23)
+    xi, info = om.solve(om.source_hat(s), tol=1e-12, max_iter=400000, adjoint=adjoint)
+    p, u, ginfo = cbs.solve(gm, s[1], s[:1], tol=1e-12, max_iter=400000, check_every=64, adjoint=adjoint)
+    assert info["converged"] and ginfo["converged"]
+    assert ginfo["iterations"] == info["iterations"]
+    assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [96, 512])
+def test_fp32_refined_1d(orc, cbs, n):
+    om, gm = _pair(orc, cbs, n)
+    s = _sources(n, 29)
+    xi, info = om.solve(om.source_hat(s), tol=1e-12, max_iter=400000)
+    p, u, ginfo = cbs.solve(gm, s[1], s[:1], tol=1e-7, prec="fp32_refined", inner_tol=1e-4,
+                            max_iter=400000)
+    assert info["converged"] and ginfo["converged"] and ginfo["rel_residual"] <= 1e-7
+    assert _rel(p, xi[-1]) <= 1e-5 and _rel(u, xi[:-1]) <= 1e-5
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_residual_1d(orc, cbs, adjoint):
+    n = 243
+    om, gm = _pair(orc, cbs, n)
+    rng = np.random.default_rng(4)
+    xi = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    s = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    shat = om.source_hat(s)
+    rel_o = om.rel_residual(shat, xi, adjoint)
+    rel_g, rp, ru = cbs.residual(gm, s[-1], s[:-1], xi[-1], xi[:-1], adjoint=adjoint, want_fields=True)
+    assert abs(rel_g - rel_o) <= 1e-12 * rel_o
+    r = shat - om.apply_A(xi, adjoint)
+    assert _rel(rp, r[-1]) <= 1e-12 and _rel(ru, r[:-1]) <= 1e-12
+
+
+def test_gradient_kernel_1d(orc, cbs):
+    n = 96
+    om, gm = _pair(orc, cbs, n)
+    rng = np.random.default_rng(6)
+
+    def rc():
+        return rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+
+    s, xi, lam = rc(), rc(), rc()
+    go = om.gradient(s, xi, lam)
+    gg = cbs.gradient(gm, s[-1], s[:-1], xi[-1], xi[:-1], lam[-1], lam[:-1])
+    for a, b in zip(gg, go):
+        assert _rel(a, b) <= 1e-12
+
+
+@pytest.mark.parametrize("alpha", [0.0, 25.0])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+def test_1d_unit_amplitude_point_source_gpu(cbs, alpha, prec):
+    """Homogeneous medium, one cell of s_p = 2 c / dx at the centre: outside
+    a wavelength from the source and outside the absorbing layer the pressure
+    is (s_p dx / 2 c_cx) exp(-i k |x|) with the complex sound speed c_cx of
+    the absorption (App. A), to the discretisation's 2e-3; without
+    absorption its modulus is 1 to 5e-3."""
+    n, pml = 384, 48
+    c0, rho0, f0 = 1500.0, 1000.0, 1e6
+    dx = c0 / f0 / 6
+    xs = n // 2
+    gm = cbs.Medium((n,), dx, OMEGA, np.full(n, c0), np.full(n, rho0), np.full(n, alpha), pml=pml)
+    sp = np.zeros(n, complex)
+    sp[xs] = 2 * c0 / dx
+    p, _, info = cbs.solve(gm, sp, tol=1e-12 if prec == "fp64" else 1e-8, prec=prec, max_iter=400000,
+                           want_u=False)
+    assert info["converged"]
+    x = (np.arange(n) - xs) * dx
+    sel = (np.abs(x) > c0 / f0) & (np.arange(n) >= pml) & (np.arange(n) < n - pml)
+    ccx = c0 / np.sqrt(1 - 2j * alpha * c0 / OMEGA)
+    ref = (2 * c0 / dx) * dx / (2 * ccx) * np.exp(-1j * (OMEGA / ccx) * np.abs(x))
+    err = np.linalg.norm(p[sel] - ref[sel]) / np.linalg.norm(ref[sel])
+    assert err < 2e-3, err
+    if alpha == 0:
+        assert np.abs(np.abs(p[sel]) - 1).max() < 5e-3

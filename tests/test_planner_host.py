@@ -39,10 +39,19 @@ def _case(name):
         s = (96, 96, 12)
         rho = np.where(np.arange(96)[:, None, None] < 40, 1000.0, 1800.0) * np.ones(s)
         return s, DX, OMEGA, np.full(s, 1500.0), rho, np.zeros(s), 0
+    if name == "random1d_512":
+        c, rho, alpha = W.small_random((512,), 11)
+        return (512,), DX, OMEGA, c, rho, alpha, 40
+    if name == "step1d_243":
+        s = (243,)
+        x = np.arange(243)
+        return s, DX, OMEGA, np.where(x < 120, 1500.0, 2100.0), np.where(x < 120, 1000.0, 1700.0), \
+            np.zeros(s), 20
     raise KeyError(name)
 
 
-CASES = ["disc2d_256", "shell3d_64", "random3d_48", "water3d_48", "uniform_no_layer", "two_densities"]
+CASES = ["disc2d_256", "shell3d_64", "random3d_48", "water3d_48", "uniform_no_layer", "two_densities",
+         "random1d_512", "step1d_243"]
 
 
 @pytest.mark.parametrize("name", CASES)
