@@ -13,6 +13,7 @@ prologue).
 * FP64 converged (1e-12) equal to 1e-10, with the same iteration count;
 * refined FP32 within 1e-5 of the oracle's converged solution;
 * the residual and gradient entry points equal the oracle's to 1e-12;
+* batched slots (graph-captured iterations) equal their single solves;
 * physics: a single-cell source of strength 2c/dx in a homogeneous medium
   radiates unit-amplitude waves (Sec. 2.3.1 source amplitude, App. A
   Green's function), the GPU solution against the closed form directly.
@@ -166,3 +167,34 @@ def test_1d_unit_amplitude_point_source_gpu(cbs, alpha, prec):
     assert err < 2e-3, err
     if alpha == 0:
         assert np.abs(np.abs(p[sel]) - 1).max() < 5e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32_refined", "fp64"])
+def test_batched_slots_1d(orc, cbs, prec):
+    """Three 1-D media (different seeds and frequencies) advanced together as
+    batched slots: each slot's result equals its single solve (same iteration
+    and outer counts, <= 1e-12)."""
+    n = 243
+    tol = 1e-6 if prec == "fp32_refined" else 1e-8
+    probs = []
+    for k, om_ in enumerate([OMEGA, 0.6 * OMEGA, 0.8 * OMEGA]):
+        c, rho, alpha = W.small_random((n,), 40 + k)
+        sp = np.zeros(n, complex)
+        sp[60 + 30 * k] = 1.0
+        probs.append((om_, c, rho, alpha, sp))
+    media = [cbs.Medium((n,), DX, om_, c, rho, alpha, pml=20) for om_, c, rho, alpha, _ in probs]
+    alone = []
+    for m, pr in zip(media, probs):
+        p, _, info = cbs.solve(m, pr[4], tol=tol, prec=prec, want_u=False)
+        assert info["converged"]
+        alone.append((p, info))
+    b = cbs.Batch((n,), DX, prec=prec, max_slots=4)
+    slots = {b.submit(m, pr[4], tol=tol): k for k, (m, pr) in enumerate(zip(media, probs))}
+    out = {}
+    while len(out) < len(probs):
+        for s in b.step(16):
+            out[slots[s]] = b.retire(s)
+    for k, (p, info) in enumerate(alone):
+        pb, _, ib = out[k]
+        assert ib["iterations"] == info["iterations"] and ib["outer"] == info["outer"]
+        assert _rel(pb, p) <= 1e-12
