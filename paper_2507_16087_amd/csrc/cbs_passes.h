@@ -636,12 +636,13 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 
 // ------------------------------------------------------ buffer access --
 // Raw buffer loads and stores: a resource descriptor in scalar registers
-// holds a base address and an extent in bytes, and each access takes only a
-// 32-bit byte offset in a vector register (dword 3 = the gfx9 raw-access
-// format word).  Planes of different fields share one offset each, so the
-// strided column passes keep one offset register per element instead of a
-// 64-bit address per element and field.  An offset beyond the extent reads
-// zero and drops the write.
+// holds a base address and an extent in bytes, and each access adds a
+// per-thread 32-bit byte offset (vector register) and a wave-uniform one
+// (scalar register), dword 3 being the gfx9 raw-access format word.  Planes
+// of different fields share the offsets, and element rows that differ by a
+// uniform step share the vector offset, so the strided column passes keep
+// one offset register per thread instead of a 64-bit address per element
+// and field.  An offset beyond the extent reads zero and drops the write.
 using bufres = __amdgpu_buffer_rsrc_t;
 template <typename T>
 __device__ __forceinline__ bufres make_res(const cx<T>* base, uint64_t bytes) {
@@ -649,16 +650,17 @@ __device__ __forceinline__ bufres make_res(const cx<T>* base, uint64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(base), (short)0, (int)n, 0x00020000);
 }
 template <typename T>
-__device__ __forceinline__ cx<T> buf_load(bufres r, uint32_t off) {
-    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+__device__ __forceinline__ cx<T> buf_load(bufres r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 template <typename T>
-__device__ __forceinline__ void buf_store(bufres r, uint32_t off, cx<T> v) {
+__device__ __forceinline__ void buf_store(bufres r, uint32_t voff, uint32_t soff, cx<T> v) {
     using V2 = unsigned int __attribute__((ext_vector_type(2)));
     using V4 = unsigned int __attribute__((ext_vector_type(4)));
-    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, 0);
-    else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, off, 0, 0);
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+    else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, voff, soff, 0);
 }
 
 // ------------------------------------- pass C: axis 0 with the propagator --
@@ -701,15 +703,18 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
     constexpr int RL = QI::r(P::S - 1);
 
     // first-stage inputs of every field of one tile, straight from HBM
+    // element (lane + u) of a column sits at vo + u es bytes: one vector
+    // offset per thread, the row step u es in a scalar register
+    const uint32_t vo = ((uint32_t)col + (uint32_t)lane * es32) * (uint32_t)sizeof(cx<T>);
+    auto soff = [&](int u) { return (uint32_t)u * es32 * (uint32_t)sizeof(cx<T>); };
     auto load = [&](cx<T> (&v)[4][E], const bufres (&res)[F]) {
 #pragma unroll
         for (int b = 0; b < N / (R0 * P::TPC); ++b)
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-                const uint32_t off =
-                    ((uint32_t)col + (uint32_t)in_index<P, -1>(lane, b, r) * es32) * (uint32_t)sizeof(cx<T>);
+                const uint32_t so = soff(in_index<P, -1>(0, b, r));
 #pragma unroll
-                for (int f = 0; f < F; ++f) v[f][b * R0 + r] = buf_load<T>(res[f], off);
+                for (int f = 0; f < F; ++f) v[f][b * R0 + r] = buf_load<T>(res[f], vo, so);
             }
     };
 
@@ -809,30 +814,39 @@ __global__ void __launch_bounds__(256) k_prop(const Slot<T>* __restrict__ slots,
             }
         }
 
-        // inverse FFT from the registers and store
+        // inverse FFT from the registers; each field is stored as soon as
+        // its transform is done, so its stores travel while the next
+        // fields are transformed
+        auto store = [&](int f) {
+#pragma unroll
+            for (int b = 0; b < N / (RL * P::TPC); ++b)
+#pragma unroll
+                for (int r = 0; r < RL; ++r)
+                    buf_store<T>(res[f], vo, soff(out_index<P, 1>(0, b, r)), v[f][b * RL + r]);
+        };
         if constexpr (NR == 4) {
             __syncthreads();
             fft_regs_multi<P, 1, 4>(v, F, lds, field_elems, ldp, col, lane, tw);
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                if (f < F) store(f);
         } else if constexpr (NR == 2) {
             __syncthreads();
             fft_regs_multi<P, 1, 2>(v, 2, lds, field_elems, ldp, col, lane, tw);
+            store(0);
+            store(1);
             __syncthreads();
             fft_regs_multi<P, 1, 2>(v + 2, F - 2, lds, field_elems, ldp, col, lane, tw);
-        }
+            store(2);
+            if (F == 4) store(3);
+        } else {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            if (f < F) {
-                if constexpr (NR == 1) {
+            for (int f = 0; f < 4; ++f) {
+                if (f < F) {
                     __syncthreads();
                     fft_regs<P, 1>(v[f], lds, ldp, col, lane, tw);
+                    store(f);
                 }
-#pragma unroll
-                for (int b = 0; b < N / (RL * P::TPC); ++b)
-#pragma unroll
-                    for (int r = 0; r < RL; ++r)
-                        buf_store<T>(res[f], ((uint32_t)col + (uint32_t)out_index<P, 1>(lane, b, r) * es32) *
-                                                 (uint32_t)sizeof(cx<T>),
-                                     v[f][b * RL + r]);
             }
         }
     };
