@@ -14,6 +14,8 @@ prologue).
 * refined FP32 within 1e-5 of the oracle's converged solution;
 * the residual and gradient entry points equal the oracle's to 1e-12;
 * batched slots (graph-captured iterations) equal their single solves;
+* a misfit gradient through torch.autograd equals the oracle's adjoint-state
+  gradient (FP64 1e-8, refined 1e-4);
 * physics: a single-cell source of strength 2c/dx in a homogeneous medium
   radiates unit-amplitude waves (Sec. 2.3.1 source amplitude, App. A
   Green's function), the GPU solution against the closed form directly.
@@ -198,3 +200,40 @@ def test_batched_slots_1d(orc, cbs, prec):
         pb, _, ib = out[k]
         assert ib["iterations"] == info["iterations"] and ib["outer"] == info["outer"]
         assert _rel(pb, p) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32_refined", 1e-4)])
+def test_autograd_gradient_1d_matches_oracle(orc, cbs, prec, tol):
+    """A 1-D misfit J = 1/2 |M p - d|^2 (source at one end, receivers near the
+    other, data from a medium with a smooth bump) differentiated through
+    torch.autograd (forward and adjoint solves, gradient kernel), against the
+    oracle's adjoint-state gradient from its own forward and adjoint solves
+    (Sec. 2.3)."""
+    import torch
+    from paper_2507_16087_amd.autograd import SolveSpec, pressure
+    n, pml = 243, 20
+    c, rho, alpha = W.small_random((n,), 61)
+    x = np.arange(n)
+    bump = np.exp(-((x - 120) / 25.0) ** 2)
+    ct, rt = c * (1 + 0.03 * bump), rho * (1 - 0.03 * bump)
+    src, rec = 30, np.arange(200, 216)
+    sp = np.zeros(n, complex)
+    sp[src] = 1.0
+    mt = orc.OracleMedium((n,), DX, OMEGA, ct, rt, alpha, pml=pml)
+    xt, _ = mt.solve(mt.source_hat(mt.pressure_source(sp)), tol=1e-13, max_iter=400000)
+    d = xt[-1][rec]
+    om = orc.OracleMedium((n,), DX, OMEGA, c, rho, alpha, pml=pml)
+    s = om.pressure_source(sp)
+    xi, _ = om.solve(om.source_hat(s), tol=1e-13, max_iter=400000)
+    g = np.zeros((2, n), complex)
+    g[1, rec] = xi[-1][rec] - d
+    lam, _ = om.solve(g, tol=1e-13, max_iter=400000, adjoint=True)
+    go = om.gradient(s, xi, lam)
+    spec = SolveSpec((n,), DX, OMEGA, pml, prec, 1e-12 if prec == "fp64" else 1e-9)
+    m = [torch.tensor(a, device="cuda", requires_grad=True) for a in (c, rho, alpha)]
+    p = pressure(*m, torch.as_tensor(sp, device="cuda"), spec).reshape(-1)
+    r = p[torch.as_tensor(rec, device="cuda")] - torch.as_tensor(d, device="cuda")
+    J = 0.5 * (r.real ** 2 + r.imag ** 2).sum()
+    J.backward()
+    for t, ref in zip(m, go):
+        assert _rel(t.grad.cpu().numpy(), ref) <= tol
