@@ -598,7 +598,14 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int G) {
 // ------------------------------------------- pass B / D: strided axis --
 // FFT along axis `axis` (< ndim - 1) of the w buffer, in place.  Tile = P
 // adjacent columns along the last axis; the first stage loads straight from
-// HBM and the last stage stores straight to HBM.
+// HBM and the last stage stores straight to HBM.  The inverse pass (DIR > 0)
+// reads and writes non-temporally: its output is next read by the fused
+// last-axis pass, which streams the whole grid anyway, so keeping it out of
+// the caches leaves the memory-side cache to what the fused pass writes for
+// the forward axis-1 pass that follows (8 % faster there, 2 % in the fused
+// pass).  The other column passes keep their lines: each writes what the
+// next one reads from the memory-side cache, and a non-temporal access to
+// lines that are then rewritten in place costs the next reader its hits.
 template <class P, int DIR, typename T>
 __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slots, Geom g, int axis,
                                                  int pcols, int ldp, int64_t es, int64_t ostride,
@@ -618,8 +625,11 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 #pragma unroll
     for (int b = 0; b < NB0; ++b)
 #pragma unroll
-        for (int r = 0; r < Seq<P, DIR>::r(0); ++r)
-            v[b * Seq<P, DIR>::r(0) + r] = w[(uint32_t)col + (uint32_t)in_index<P, DIR>(lane, b, r) * es32];
+        for (int r = 0; r < Seq<P, DIR>::r(0); ++r) {
+            const GLOBAL cx<T>* q = w + ((uint32_t)col + (uint32_t)in_index<P, DIR>(lane, b, r) * es32);
+            if constexpr (DIR > 0) v[b * Seq<P, DIR>::r(0) + r] = ld_nt(q);
+            else v[b * Seq<P, DIR>::r(0) + r] = *q;
+        }
     // twiddles in LDS after the tile (first used after the first stage's barrier)
     cx<T>* tw_l = reinterpret_cast<cx<T>*>(smem_raw + tile_bytes<T>((size_t)P::N * ldp));
     for (int i = tid; i < P::N; i += blockDim.x) tw_l[i] = gmem(s.tw[axis])[i];
@@ -630,8 +640,11 @@ __global__ void __launch_bounds__(256) k_strided(const Slot<T>* __restrict__ slo
 #pragma unroll
     for (int b = 0; b < NBl; ++b)
 #pragma unroll
-        for (int r = 0; r < Rl; ++r)
-            w[(uint32_t)col + (uint32_t)out_index<P, DIR>(lane, b, r) * es32] = v[b * Rl + r];
+        for (int r = 0; r < Rl; ++r) {
+            GLOBAL cx<T>* q = w + ((uint32_t)col + (uint32_t)out_index<P, DIR>(lane, b, r) * es32);
+            if constexpr (DIR > 0) st_nt(q, v[b * Rl + r]);
+            else *q = v[b * Rl + r];
+        }
 }
 
 // ------------------------------------------------------ buffer access --
