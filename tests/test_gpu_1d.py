@@ -14,6 +14,7 @@ prologue).
 * refined FP32 within 1e-5 of the oracle's converged solution;
 * the residual and gradient entry points equal the oracle's to 1e-12;
 * batched slots (graph-captured iterations) equal their single solves;
+* the collocated-grid variant's iterates equal the oracle's;
 * a misfit gradient through torch.autograd equals the oracle's adjoint-state
   gradient (FP64 1e-8, refined 1e-4);
 * physics: a single-cell source of strength 2c/dx in a homogeneous medium
@@ -237,3 +238,19 @@ def test_autograd_gradient_1d_matches_oracle(orc, cbs, prec, tol):
     J.backward()
     for t, ref in zip(m, go):
         assert _rel(t.grad.cpu().numpy(), ref) <= tol
+
+
+@pytest.mark.parametrize("n", [96, 243])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_collocated_iterates_1d(orc, cbs, n, adjoint):
+    """The collocated-grid variant (App. B first matrix) in one dimension:
+    FP64 iterates against the oracle's, which applies the collocated matrix
+    explicitly."""
+    c, rho, alpha = W.small_random((n,), 3)
+    om = orc.OracleMedium((n,), DX, OMEGA, c, rho, alpha, pml=4, collocated=True)
+    gm = cbs.Medium((n,), DX, OMEGA, c, rho, alpha, pml=4, collocated=True)
+    s = _sources(n, 31)
+    xi, _ = om.solve(om.source_hat(s), tol=0.0, max_iter=40, adjoint=adjoint)
+    p, u, info = cbs.solve(gm, s[1], s[:1], tol=0.0, max_iter=40, adjoint=adjoint)
+    assert info["iterations"] == 40
+    assert _rel(p, xi[-1]) <= 1e-10 and _rel(u, xi[:-1]) <= 1e-10
