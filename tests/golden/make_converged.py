@@ -20,11 +20,12 @@ state of the previous chunk, and stores what the GPU tests compare against:
 
 Usage:  python tests/golden/make_converged.py random128 [--tol 1e-10]
                                                [--budget-hours H] [--chunk K]
-                                               [--max-iters K]
+                                               [--max-iters K] [--ckpt-dir DIR]
         python tests/golden/make_converged.py shell256 ...
 
-The scaled state is checkpointed under ``--ckpt-dir`` after every chunk, so a
-killed run resumes where it stopped.  ``OMP_NUM_THREADS`` sets the oracle's
+With ``--ckpt-dir DIR`` the scaled state is checkpointed in DIR after every
+chunk, so a killed run resumes where it stopped (without it, nothing is saved
+between chunks).  ``OMP_NUM_THREADS`` sets the oracle's
 thread count.
 """
 from __future__ import annotations
@@ -83,16 +84,19 @@ def main() -> None:
     ap.add_argument("--budget-hours", type=float, default=1e9)
     ap.add_argument("--max-iters", type=int, default=0,
                     help="stop after this many iterations in all (0: no cap)")
-    ap.add_argument("--ckpt-dir", default=os.path.join(ROOT, "_work", "ckpt"))
+    ap.add_argument("--ckpt-dir", default=None,
+                    help="directory for the resumable checkpoint (default: none)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
 
     prob, focus = problem(a.workload)
     shape = prob.shape
     out_path = a.out or os.path.join(HERE, f"oracle_{a.workload}.npz")
-    os.makedirs(a.ckpt_dir, exist_ok=True)
-    ck_state = os.path.join(a.ckpt_dir, f"{a.workload}_x.npy")
-    ck_meta = os.path.join(a.ckpt_dir, f"{a.workload}_meta.json")
+    ck_state = ck_meta = None
+    if a.ckpt_dir:
+        os.makedirs(a.ckpt_dir, exist_ok=True)
+        ck_state = os.path.join(a.ckpt_dir, f"{a.workload}_x.npy")
+        ck_meta = os.path.join(a.ckpt_dir, f"{a.workload}_meta.json")
 
     m = orc.OracleMedium(shape, prob.dx, prob.omega, prob.c, prob.rho, prob.alpha,
                          pml=prob.pml_cells)
@@ -102,7 +106,7 @@ def main() -> None:
     root = np.sqrt(lam).reshape(4, 1, 1, 1)
 
     iters, rel, x0 = 0, float("inf"), None
-    if os.path.exists(ck_state) and os.path.exists(ck_meta):
+    if ck_state and os.path.exists(ck_state) and os.path.exists(ck_meta):
         meta = json.load(open(ck_meta))
         iters, rel = int(meta["iterations"]), float(meta["rel_update"])
         x0 = np.load(ck_state)
@@ -117,11 +121,12 @@ def main() -> None:
         iters += info["iterations"]
         rel = info["rel_update"]
         x0 = xi * root                                  # scaled state x = C^{1/2} xi
-        np.save(ck_state + ".tmp.npy", x0)
-        os.replace(ck_state + ".tmp.npy", ck_state)
-        with open(ck_meta + ".tmp", "w") as f:
-            json.dump(dict(iterations=iters, rel_update=rel), f)
-        os.replace(ck_meta + ".tmp", ck_meta)
+        if ck_state:
+            np.save(ck_state + ".tmp.npy", x0)
+            os.replace(ck_state + ".tmp.npy", ck_state)
+            with open(ck_meta + ".tmp", "w") as f:
+                json.dump(dict(iterations=iters, rel_update=rel), f)
+            os.replace(ck_meta + ".tmp", ck_meta)
         print(f"{a.workload}: {iters} iterations, rel update {rel:.3e}, "
               f"{(time.time() - t0) / max(info['iterations'], 1):.2f} s/iteration", flush=True)
         if info["converged"]:
