@@ -10,7 +10,7 @@ benchmark times (autotuned plans of the same shapes).
   residual of 1e-7 is within 1e-5 of the FP64 GPU solution at 1e-8.  The
   FP64 GPU path stands in for a converged oracle here: the oracle's own
   256^3 solve would need some 40 000 iterations at seconds each on the host,
-  so its contact at this size is iterate parity (here and, after 1000
+  so its contact at this size is iterate parity (here and, after 2600
   iterations, in test_gpu_oracle_refs.py) and the residual check.
 """
 import numpy as np
